@@ -1,0 +1,20 @@
+"""Seeded synthetic hyperspectral cubes.
+
+This module only draws random numbers and arranges them into cubes. It holds
+none of the PCA arithmetic (no means, covariances, rotations or projections),
+so both the FP64 oracle's tests and the GPU path's tests/benchmarks can use it
+without sharing any of the method with each other.
+"""
+
+from .cubes import (  # noqa: F401
+    CONFIGS,
+    batch_shapes,
+    endmember_spectra,
+    make_batch,
+    make_config,
+    mixture_cube,
+    planted_cube,
+    planted_spectrum,
+    radiance_cube_u16,
+    random_symmetric,
+)
