@@ -1,0 +1,166 @@
+/*
+ * pca.h - C ABI of the MI355X (gfx950) Jacobi-PCA library, libpca.so.
+ *
+ * The library computes the principal component analysis of a hyperspectral
+ * cube as laid out in Algorithm 1 of Martel et al., "Implementation of the
+ * Principal Component Analysis onto High-Performance Computer Facilities for
+ * Hyperspectral Dimensionality Reduction" (Section 2): band-mean removal,
+ * the bands x bands covariance over all pixels, a cyclic Jacobi
+ * eigendecomposition of that covariance, and the projection of every pixel
+ * onto the leading eigenvectors.
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is a DEVICE pointer owned by the caller (the
+ *     library never allocates, frees or copies to the host). Matrices are
+ *     row-major. The cube is band-interleaved-by-pixel: pixel p, band b is
+ *     element p * ld_y + b.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Every call only enqueues kernels on it and returns without waiting.
+ *   - Argument checks are synchronous and touch no device memory; a failed
+ *     check returns PCA_ERR_ARG / PCA_ERR_UNSUPPORTED / PCA_ERR_WORKSPACE and
+ *     enqueues nothing. A launch failure returns PCA_ERR_HIP.
+ *   - Numerical outcomes (non-convergence, non-finite data) are reported in
+ *     the device-resident pca_info written by pca_jacobi_eigh.
+ *   - Results are deterministic: every reduction runs in a fixed order, no
+ *     floating-point atomics are used.
+ *   - Calls on one stream run in order; calls sharing a workspace must not
+ *     overlap on different streams.
+ *   - Limits: 2 <= n_bands <= 256, n_pixels >= 2, pointers 16-byte aligned,
+ *     workspace 256-byte aligned.
+ */
+#ifndef PCA_H
+#define PCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCA_OK = 0,
+    PCA_ERR_ARG = 1,          /* NULL pointer, size out of range, misalignment */
+    PCA_ERR_UNSUPPORTED = 2,  /* valid request that this build does not handle */
+    PCA_ERR_WORKSPACE = 3,    /* workspace smaller than pca_workspace_size */
+    PCA_ERR_HIP = 4           /* a HIP launch or attribute call failed */
+} pca_status;
+
+/* Element type of the cube. */
+typedef enum {
+    PCA_IN_F32 = 0,           /* float32 */
+    PCA_IN_U16 = 1            /* uint16 (e.g. raw radiance counts), read as exact integers */
+} pca_in_dtype;
+
+/* Arithmetic of the covariance products (the sums are always combined in
+ * float64 across pixel chunks). */
+typedef enum {
+    PCA_COV_F32 = 0,          /* float32 products, float32 MFMA accumulation */
+    PCA_COV_BF16X3 = 1,       /* split x = hi + lo into two bfloat16 terms;
+                                 hi*hi + hi*lo + lo*hi with bfloat16 MFMA and
+                                 float32 accumulation (lo*lo dropped) */
+    PCA_COV_BF16X4 = 2        /* as BF16X3 plus lo*lo: the exact product of
+                                 the 16-significant-bit split */
+} pca_cov_mode;
+
+/* Operation selector for pca_workspace_size. */
+typedef enum {
+    PCA_OP_CENTER = 0,
+    PCA_OP_COVARIANCE = 1,
+    PCA_OP_JACOBI = 2,
+    PCA_OP_PROJECT = 3,
+    PCA_OP_BACKWARD = 4
+} pca_op;
+
+/* Written on the device by pca_jacobi_eigh (copy it back to read it). */
+typedef struct {
+    int32_t sweeps;      /* sweeps carried out */
+    int32_t converged;   /* 1 when a stop rule was met before max_sweeps */
+    int32_t nonfinite;   /* 1 when C held a NaN or an infinity (outputs are then NaN) */
+    int32_t floor_hit;   /* 1 when the last sweep applied no rotation (float32 floor) */
+    double off_rel;      /* final sqrt(sum_{i!=j} a_ij^2) / ||C||_F */
+    int64_t rotations;   /* rotations applied */
+    int32_t steps;       /* parallel rotation steps carried out */
+    int32_t n_bands;
+} pca_info;
+
+/* Human-readable name of a status code (static storage). */
+const char *pca_status_string(pca_status s);
+
+/*
+ * Bytes of workspace that `op` needs for the given sizes (mode: a
+ * pca_cov_mode for PCA_OP_COVARIANCE; max_sweeps: for PCA_OP_JACOBI).
+ */
+pca_status pca_workspace_size(int op, int64_t n_pixels, int32_t n_bands, int32_t k,
+                              int32_t mode, int32_t max_sweeps, size_t *bytes);
+
+/*
+ * Band-average removal (Algorithm 1, line 2; the per-band average of the
+ * GPU design's Code 4.2.1 and its subtraction, Code 4.2.2).
+ *   Y     [n_pixels][ld_y] cube of type dt.
+ *   mean  [n_bands] float32 out: mu_b = (1/N) sum_p Y[p, b], summed in float64.
+ *   X     [n_pixels][ld_x] float32 out: Y - 1 mu^T, or NULL to write only mean.
+ *   ws    workspace of pca_workspace_size(PCA_OP_CENTER, ...) bytes.
+ */
+pca_status pca_center(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y,
+                      float *mean, float *X, int64_t ld_x, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/*
+ * Covariance C = X^T X / (N - 1) of the centred cube (Algorithm 1, line 3,
+ * normalised by PIXELS - 1 as in Code 4.3), with the centring fused: the cube
+ * is read once. Pixels are processed in chunks; each chunk accumulates
+ * sum (y - s)(y - s)^T and sum (y - s) about its first pixel s on chip, and
+ * the chunk results are combined in float64 in chunk order into the centred
+ * second moment (exact algebra, no cancellation against a global mean).
+ *   Y                  [n_pixels][ld_y] cube of type dt.
+ *   input_is_centered  1: Y already is X (C = Y^T Y / (N-1), mean not written);
+ *                      0: centre on the fly.
+ *   mean               [n_bands] float32 out (may be NULL).
+ *   mode               a pca_cov_mode.
+ *   C                  [n_bands][n_bands] float32 out, exactly symmetric.
+ *   ws                 workspace of pca_workspace_size(PCA_OP_COVARIANCE, ...).
+ */
+pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y,
+                          int32_t input_is_centered, float *mean, int mode, float *C,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * All eigenpairs of the symmetric C by the cyclic Jacobi method (Section 2,
+ * equations (2)-(10)): one workgroup holds the matrix in LDS and applies
+ * n_bands/2 disjoint rotations per parallel step in round-robin order (the
+ * parallel-rotation property stated at the end of Section 2), n_bands - 1
+ * steps per sweep. Rotation angles use equations (2)-(5) with (7) in the
+ * cancellation-free form; fp64_angles = 1 evaluates them (and the diagonal)
+ * in float64. A rotation is skipped when |a_pq| <= 2^-24 sqrt(|a_pp a_qq|)
+ * or |a_pq| <= 2^-24 ||C||_F / n_bands. Stops before a sweep when
+ * off(A)/||C||_F <= tol, after a sweep that applied no rotation, or after
+ * max_sweeps sweeps.
+ * Eigenvalues are sorted in descending order (stable), eigenvector columns
+ * permuted to match (Code 4.4.3), and each eigenvector's sign fixed so that
+ * its largest-magnitude entry is positive (lowest index on ties).
+ *   C        [n_bands][n_bands] float32, symmetric (the upper triangle is read).
+ *   eigvals  [n_bands] float32 out, descending.
+ *   V        [n_bands][n_bands] float32 out; column j is eigenvector j.
+ *   info     device pca_info out (may be NULL).
+ *   ws       workspace of pca_workspace_size(PCA_OP_JACOBI, ..., max_sweeps).
+ */
+pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t max_sweeps,
+                           int32_t fp64_angles, float *eigvals, float *V, pca_info *info,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Projection onto the first k eigenvectors (Algorithm 1, lines 5-6):
+ *   Q[p, i] = sum_b (Y[p, b] - mean[b]) V[b, i],  i < k.
+ *   mean  [n_bands] float32, or NULL when Y is already centred.
+ *   V     [n_bands][n_bands] float32, column i = eigenvector i.
+ *   Q     [n_pixels][k] float32 out. 1 <= k <= n_bands.
+ */
+pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y,
+                       const float *mean, const float *V, int32_t k, float *Q, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCA_H */

@@ -1,0 +1,30 @@
+"""MI355X (gfx950) Jacobi-PCA for hyperspectral cubes.
+
+The compute path is libpca.so (hand-written HIP kernels behind a C ABI,
+include/pca.h); this package only marshals torch tensors into it.
+"""
+
+from ._lib import (  # noqa: F401
+    COV_MODES,
+    LIB_PATH,
+    PCA_COV_BF16X3,
+    PCA_COV_BF16X4,
+    PCA_COV_F32,
+    PCA_IN_F32,
+    PCA_IN_U16,
+    PCA_OP_CENTER,
+    PCA_OP_COVARIANCE,
+    PCA_OP_JACOBI,
+    PCA_OP_PROJECT,
+    PCAError,
+    library,
+    new_info,
+    pca_center,
+    pca_covariance,
+    pca_jacobi_eigh,
+    pca_project,
+    pca_workspace_size,
+    read_info,
+    workspace,
+)
+from .api import DEFAULT_MAX_SWEEPS, DEFAULT_TOL, PCAPipeline, PCAResult, run  # noqa: F401

@@ -1,0 +1,75 @@
+"""High-level driver: the four stages of Algorithm 1 on one cube, through
+the C ABI. Buffers come from torch's allocator; all work is in libpca."""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+DEFAULT_TOL = 1e-6          # relative off-norm stop for the float32 Jacobi
+DEFAULT_MAX_SWEEPS = 30
+
+
+@dataclass
+class PCAResult:
+    mean: torch.Tensor      # [M] float32
+    C: torch.Tensor         # [M, M] float32
+    eigvals: torch.Tensor   # [M] float32, descending
+    V: torch.Tensor         # [M, M] float32, column j = eigenvector j
+    Q: torch.Tensor         # [N, k] float32
+    info: torch.Tensor      # device pca_info
+
+    def read_info(self) -> dict:
+        return L.read_info(self.info)
+
+
+class PCAPipeline:
+    """Preallocated buffers and workspaces for cubes of one shape; forward()
+    only enqueues kernels (no allocation, no synchronisation), so it can be
+    captured in a HIP graph."""
+
+    def __init__(self, n_pixels: int, n_bands: int, k: int, mode: str = "f32",
+                 tol: float = DEFAULT_TOL, max_sweeps: int = DEFAULT_MAX_SWEEPS,
+                 fp64_angles: bool = True, device="cuda"):
+        self.n, self.m, self.k = int(n_pixels), int(n_bands), int(k)
+        self.mode = L.COV_MODES[mode] if isinstance(mode, str) else int(mode)
+        self.tol, self.max_sweeps, self.fp64_angles = float(tol), int(max_sweeps), bool(fp64_angles)
+        dev = torch.device(device)
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.mean = torch.empty(self.m, **f32)
+        self.C = torch.empty(self.m, self.m, **f32)
+        self.eigvals = torch.empty(self.m, **f32)
+        self.V = torch.empty(self.m, self.m, **f32)
+        self.Q = torch.empty(self.n, self.k, **f32)
+        self.info = L.new_info(dev)
+        self.ws_cov = L.workspace(L.pca_workspace_size(L.PCA_OP_COVARIANCE, self.n, self.m, mode=self.mode), dev)
+        self.ws_jac = L.workspace(L.pca_workspace_size(L.PCA_OP_JACOBI, self.n, self.m,
+                                                       max_sweeps=self.max_sweeps), dev)
+
+    def covariance(self, Y):
+        L.pca_covariance(Y, self.C, self.mean, self.mode, False, self.ws_cov)
+
+    def eigh(self):
+        L.pca_jacobi_eigh(self.C, self.eigvals, self.V, self.tol, self.max_sweeps, self.fp64_angles,
+                          self.info, self.ws_jac)
+
+    def project(self, Y):
+        L.pca_project(Y, self.mean, self.V, self.k, self.Q)
+
+    def forward(self, Y) -> PCAResult:
+        if tuple(Y.shape) != (self.n, self.m):
+            raise ValueError(f"cube shape {tuple(Y.shape)} != ({self.n}, {self.m})")
+        self.covariance(Y)
+        self.eigh()
+        self.project(Y)
+        return PCAResult(self.mean, self.C, self.eigvals, self.V, self.Q, self.info)
+
+
+def run(Y: torch.Tensor, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
+        max_sweeps: int = DEFAULT_MAX_SWEEPS, fp64_angles: bool = True) -> PCAResult:
+    """PCA of one device cube Y [pixels, bands] (float32 or uint16)."""
+    pipe = PCAPipeline(Y.shape[0], Y.shape[1], k, mode, tol, max_sweeps, fp64_angles, Y.device)
+    return pipe.forward(Y)

@@ -1,0 +1,146 @@
+// C ABI of libpca: argument validation, workspace layout and kernel launches.
+// Declarations and the contract of every entry point are in include/pca.h.
+#include <math.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+#include "pca.h"
+
+namespace {
+
+constexpr size_t kWsAlign = 256;
+inline size_t al(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+inline bool valid_dt(int dt) { return dt == PCA_IN_F32 || dt == PCA_IN_U16; }
+
+inline pca_status check_cube(const void *Y, int dt, int64_t n, int32_t m, int64_t ld)
+{
+    if (!Y || !valid_dt(dt)) return PCA_ERR_ARG;
+    if (n < 2 || m < 2 || m > pca::kMaxBands || ld < m) return PCA_ERR_ARG;
+    if (!aligned(Y, dt == PCA_IN_F32 ? 4 : 2)) return PCA_ERR_ARG;
+    return PCA_OK;
+}
+
+inline pca_status hip_status(hipError_t e) { return e == hipSuccess ? PCA_OK : PCA_ERR_HIP; }
+
+size_t center_ws(const pca::CovPlan &p, int m) { return al(p.bytes_sum) + al((size_t)m * sizeof(double)); }
+size_t cov_ws(const pca::CovPlan &p) { return al(p.bytes_S) + al(p.bytes_sum); }
+size_t jac_ws(const pca::JacPlan &p) { return al(p.bytes_log) + al(p.bytes_lam) + al(p.bytes_vu) + al(p.bytes_info); }
+
+}  // namespace
+
+extern "C" {
+
+const char *pca_status_string(pca_status s)
+{
+    switch (s) {
+    case PCA_OK: return "PCA_OK";
+    case PCA_ERR_ARG: return "PCA_ERR_ARG: invalid argument";
+    case PCA_ERR_UNSUPPORTED: return "PCA_ERR_UNSUPPORTED: unsupported request";
+    case PCA_ERR_WORKSPACE: return "PCA_ERR_WORKSPACE: workspace too small";
+    case PCA_ERR_HIP: return "PCA_ERR_HIP: HIP runtime error";
+    }
+    return "unknown pca_status";
+}
+
+pca_status pca_workspace_size(int op, int64_t n_pixels, int32_t n_bands, int32_t k, int32_t mode,
+                              int32_t max_sweeps, size_t *bytes)
+{
+    (void)k;
+    if (!bytes || n_bands < 2 || n_bands > pca::kMaxBands) return PCA_ERR_ARG;
+    switch (op) {
+    case PCA_OP_CENTER:
+        if (n_pixels < 2) return PCA_ERR_ARG;
+        *bytes = center_ws(pca::cov_plan(n_pixels, n_bands), n_bands);
+        return PCA_OK;
+    case PCA_OP_COVARIANCE:
+        if (n_pixels < 2 || mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
+        *bytes = cov_ws(pca::cov_plan(n_pixels, n_bands));
+        return PCA_OK;
+    case PCA_OP_JACOBI:
+        if (max_sweeps < 0) return PCA_ERR_ARG;
+        *bytes = jac_ws(pca::jac_plan(n_bands, max_sweeps));
+        return PCA_OK;
+    case PCA_OP_PROJECT:
+        *bytes = 0;
+        return PCA_OK;
+    default:
+        return PCA_ERR_UNSUPPORTED;
+    }
+}
+
+pca_status pca_center(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y, float *mean,
+                      float *X, int64_t ld_x, void *ws, size_t ws_bytes, void *stream)
+{
+    pca_status s = check_cube(Y, dt, n_pixels, n_bands, ld_y);
+    if (s != PCA_OK) return s;
+    if (!mean || !ws || !aligned(ws, kWsAlign) || !aligned(mean, 4)) return PCA_ERR_ARG;
+    if (X && (ld_x < n_bands || !aligned(X, 4))) return PCA_ERR_ARG;
+    const pca::CovPlan plan = pca::cov_plan(n_pixels, n_bands);
+    if (ws_bytes < center_ws(plan, n_bands)) return PCA_ERR_WORKSPACE;
+    char *w = static_cast<char *>(ws);
+    double *partSum = reinterpret_cast<double *>(w);
+    double *mean64 = reinterpret_cast<double *>(w + al(plan.bytes_sum));
+    return hip_status(pca::launch_center(Y, dt, n_pixels, n_bands, ld_y, mean, X, ld_x, plan, partSum, mean64,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y,
+                          int32_t input_is_centered, float *mean, int mode, float *C, void *ws,
+                          size_t ws_bytes, void *stream)
+{
+    pca_status s = check_cube(Y, dt, n_pixels, n_bands, ld_y);
+    if (s != PCA_OK) return s;
+    if (!C || !ws || !aligned(ws, kWsAlign) || !aligned(C, 4) || (mean && !aligned(mean, 4))) return PCA_ERR_ARG;
+    if (mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
+    if (input_is_centered != 0 && input_is_centered != 1) return PCA_ERR_ARG;
+    const pca::CovPlan plan = pca::cov_plan(n_pixels, n_bands);
+    if (ws_bytes < cov_ws(plan)) return PCA_ERR_WORKSPACE;
+    char *w = static_cast<char *>(ws);
+    float *partS = reinterpret_cast<float *>(w);
+    double *partSum = reinterpret_cast<double *>(w + al(plan.bytes_S));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = pca::launch_cov_partial(Y, dt, n_pixels, n_bands, ld_y, input_is_centered, mode, plan, partS,
+                                           partSum, st);
+    if (e != hipSuccess) return PCA_ERR_HIP;
+    return hip_status(pca::launch_cov_finalize(Y, dt, n_pixels, n_bands, ld_y, input_is_centered, plan, partS,
+                                               partSum, C, mean, st));
+}
+
+pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t max_sweeps, int32_t fp64_angles,
+                           float *eigvals, float *V, pca_info *info, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!C || !eigvals || !V || !ws) return PCA_ERR_ARG;
+    if (n_bands < 2 || n_bands > pca::kMaxBands) return PCA_ERR_ARG;
+    if (!(tol >= 0.0) || !isfinite(tol) || max_sweeps < 0 || max_sweeps > 100000) return PCA_ERR_ARG;
+    if (fp64_angles != 0 && fp64_angles != 1) return PCA_ERR_ARG;
+    if (!aligned(ws, kWsAlign) || !aligned(C, 4) || !aligned(eigvals, 4) || !aligned(V, 4)) return PCA_ERR_ARG;
+    if (info && !aligned(info, 8)) return PCA_ERR_ARG;
+    const pca::JacPlan plan = pca::jac_plan(n_bands, max_sweeps);
+    if (ws_bytes < jac_ws(plan)) return PCA_ERR_WORKSPACE;
+    char *w = static_cast<char *>(ws);
+    float2 *rlog = reinterpret_cast<float2 *>(w);
+    w += al(plan.bytes_log);
+    double *lam_u = reinterpret_cast<double *>(w);
+    w += al(plan.bytes_lam);
+    float *Vu = reinterpret_cast<float *>(w);
+    w += al(plan.bytes_vu);
+    pca_info *info_ws = reinterpret_cast<pca_info *>(w);
+    return hip_status(pca::launch_jacobi(C, n_bands, tol, max_sweeps, fp64_angles, plan, lam_u, rlog, Vu, info_ws,
+                                         eigvals, V, info, static_cast<hipStream_t>(stream)));
+}
+
+pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,
+                       const float *V, int32_t k, float *Q, void *stream)
+{
+    pca_status s = check_cube(Y, dt, n_pixels, n_bands, ld_y);
+    if (s != PCA_OK) return s;
+    if (!V || !Q || k < 1 || k > n_bands) return PCA_ERR_ARG;
+    if (!aligned(V, 4) || !aligned(Q, 4) || (mean && !aligned(mean, 4))) return PCA_ERR_ARG;
+    return hip_status(pca::launch_project(Y, dt, n_pixels, n_bands, ld_y, mean, V, k, Q,
+                                          static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,391 @@
+// Covariance of the centred cube, C = X^T X / (N - 1) (Algorithm 1, line 3;
+// normalised by PIXELS - 1 as in Code 4.3), with the band-mean removal
+// (Algorithm 1, line 2) fused so that the cube is streamed from HBM once.
+//
+// Pass 1 (cov_partial): one workgroup per chunk of pixels. Each chunk is
+// shifted by its own first pixel s_w, and the workgroup accumulates on chip
+//   S_w = sum_{p in w} (y_p - s_w)(y_p - s_w)^T   (upper-triangle 32x32 blocks)
+//   t_w = sum_{p in w} (y_p - s_w)               (float64 per band)
+// with MFMA: float32 products (v_mfma_f32_32x32x2_f32) or the split-bfloat16
+// products (v_mfma_f32_32x32x16_bf16) of x = hi + lo. Splitting the sum over
+// pixel chunks and adding the chunk results mirrors the pixel split of
+// equation (17); only the upper triangle is formed, as the manycore design
+// does for the symmetric result.
+// Pass 2 (cov_finalize): in float64 and chunk order,
+//   mu = (1/N) sum_w (n_w s_w + t_w),  e_w = s_w - mu,
+//   N_2 = sum_w [S_w + t_w e_w^T + e_w t_w^T + n_w e_w e_w^T]
+//       = sum_p (y_p - mu)(y_p - mu)^T          (exact algebra),
+//   C = N_2 / (N - 1), mirrored to a full symmetric matrix.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "loader.hpp"
+
+namespace pca {
+
+namespace {
+
+constexpr int kThreads = 256;   // 4 waves; wave w loads pixel group w of a stage
+constexpr int KT = kCovTile;    // 32 pixels per stage = 4 groups of 8
+constexpr int kSlots = 9;       // accumulator blocks per wave (36 blocks / 4 waves)
+constexpr int kFlush = 8;       // stages per first-level MFMA accumulation (float32 mode)
+constexpr int kBfPitch = KT + 8;  // bf16 per band row in LDS (80 bytes)
+
+enum { MODE_F32 = 0, MODE_BF16X3 = 1, MODE_BF16X4 = 2 };
+
+// Pixel-major float32 stage pitch (floats): pitch % 64 == 32 so the two
+// half-waves of an MFMA operand read fall on disjoint LDS banks.
+__host__ __device__ constexpr int f32_pitch(int mpad) { return (mpad % 64 == 0) ? mpad + 32 : mpad; }
+
+// Static id of the upper-triangle block (bi, bj), bi <= bj < 8.
+__host__ __device__ constexpr int static_block(int bi, int bj) { return bi * 8 - bi * (bi - 1) / 2 + (bj - bi); }
+// Compact id for nb blocks per side (the layout of the partial results).
+__device__ inline int compact_block(int bi, int bj, int nb) { return bi * nb - bi * (bi - 1) / 2 + (bj - bi); }
+
+__device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
+{
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+template <typename T, int VEC, int MODE>
+__global__ __launch_bounds__(kThreads) void cov_partial_kernel(
+    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
+    int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum)
+{
+    constexpr int kF32Max = KT * (256 + 32);
+    constexpr int kBfMax = 256 * kBfPitch;
+    __shared__ __attribute__((aligned(16))) float tileF[MODE == MODE_F32 ? kF32Max : 4];
+    __shared__ __attribute__((aligned(16))) __bf16 hiT[MODE == MODE_F32 ? 8 : kBfMax];
+    __shared__ __attribute__((aligned(16))) __bf16 loT[MODE == MODE_F32 ? 8 : kBfMax];
+    __shared__ double red[4][256];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t c = blockIdx.x;
+    const int64_t pbeg = c * chunk;
+    const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
+    const int pf = f32_pitch(mpad);
+
+    // Shift of this chunk: its first pixel (zero when the cube is centred).
+    float shift[4];
+    double sums[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int b = slot_band<VEC>(lane, s);
+        shift[s] = (!centered && b < m) ? load_elem(Y + pbeg * ld + b) : 0.f;
+        sums[s] = 0.0;
+    }
+
+    // float32 products accumulate in two levels (the MFMA accumulator is
+    // emptied into acc2 every kFlush stages) to keep rounding chains short;
+    // a split-bfloat16 MFMA already sums 16 pixels per instruction, so one
+    // level keeps its chains as short.
+    constexpr bool kTwoLevel = MODE == MODE_F32;
+    constexpr int kSlots2 = kTwoLevel ? kSlots : 1;
+    f32x16 acc[kSlots], acc2[kSlots2];
+#pragma unroll
+    for (int e = 0; e < kSlots; ++e) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[e][r] = 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < kSlots2; ++e) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc2[e][r] = 0.f;
+    }
+
+    float v[8][4];
+    load_group<T, VEC>(Y, ld, pbeg + 8 * wave, pend, m, lane, v);
+
+    const int64_t nst = (pend - pbeg + KT - 1) / KT;
+    for (int64_t st = 0; st < nst; ++st) {
+        const int64_t g0 = pbeg + st * KT + 8 * wave;  // first pixel of this wave's group
+        const int64_t nval64 = pend - g0;
+        const int nval = nval64 < 0 ? 0 : (nval64 > 8 ? 8 : (int)nval64);
+
+        // Centre about the chunk shift, accumulate band sums, stage in LDS.
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int b = slot_band<VEC>(lane, s);
+            float x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = (i < nval) ? v[i][s] - shift[s] : 0.f;
+            double ts = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) ts += (double)x[i];
+            sums[s] += ts;
+            if constexpr (MODE == MODE_F32) {
+                if constexpr (VEC == 1) {
+                    if (b < mpad) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) tileF[(8 * wave + i) * pf + b] = x[i];
+                    }
+                }
+            } else {
+                if (b < mpad) {
+                    bf16x8 h, l;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        __bf16 hh, ll;
+                        split_bf16(x[i], hh, ll);
+                        h[i] = hh;
+                        l[i] = ll;
+                    }
+                    *reinterpret_cast<bf16x8 *>(&hiT[b * kBfPitch + 8 * wave]) = h;
+                    *reinterpret_cast<bf16x8 *>(&loT[b * kBfPitch + 8 * wave]) = l;
+                }
+            }
+        }
+        if constexpr (MODE == MODE_F32 && VEC == 4) {
+            const int b = 4 * lane;
+            if (b < mpad) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    f32x4 q;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) q[s] = (i < nval) ? v[i][s] - shift[s] : 0.f;
+                    *reinterpret_cast<f32x4 *>(&tileF[(8 * wave + i) * pf + b]) = q;
+                }
+            }
+        }
+
+        // Prefetch the next stage while this one is multiplied.
+        if (st + 1 < nst) load_group<T, VEC>(Y, ld, g0 + KT, pend, m, lane, v);
+        __syncthreads();
+
+        if constexpr (MODE == MODE_F32) {
+#pragma unroll 2
+            for (int kk = 0; kk < KT / 2; ++kk) {
+                float op[8];
+                const int row = 2 * kk + (lane >> 5);
+#pragma unroll
+                for (int bb = 0; bb < 8; ++bb)
+                    op[bb] = (bb < nb) ? tileF[row * pf + 32 * bb + (lane & 31)] : 0.f;
+#pragma unroll
+                for (int bi = 0; bi < 8; ++bi) {
+#pragma unroll
+                    for (int bj = bi; bj < 8; ++bj) {
+                        const int E = static_block(bi, bj);
+                        if ((E & 3) != wave || bj >= nb) continue;
+                        acc[E >> 2] = __builtin_amdgcn_mfma_f32_32x32x2f32(op[bi], op[bj], acc[E >> 2], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KT / 16; ++kk) {
+                bf16x8 oh[8], ol[8];
+                const int col = 16 * kk + 8 * (lane >> 5);
+#pragma unroll
+                for (int bb = 0; bb < 8; ++bb) {
+                    if (bb < nb) {
+                        const int row = 32 * bb + (lane & 31);
+                        oh[bb] = *reinterpret_cast<const bf16x8 *>(&hiT[row * kBfPitch + col]);
+                        ol[bb] = *reinterpret_cast<const bf16x8 *>(&loT[row * kBfPitch + col]);
+                    } else {
+                        oh[bb] = bf16x8{};
+                        ol[bb] = bf16x8{};
+                    }
+                }
+#pragma unroll
+                for (int bi = 0; bi < 8; ++bi) {
+#pragma unroll
+                    for (int bj = bi; bj < 8; ++bj) {
+                        const int E = static_block(bi, bj);
+                        if ((E & 3) != wave || bj >= nb) continue;
+                        f32x16 a = acc[E >> 2];
+                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(oh[bi], oh[bj], a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(oh[bi], ol[bj], a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ol[bi], oh[bj], a, 0, 0, 0);
+                        if constexpr (MODE == MODE_BF16X4)
+                            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ol[bi], ol[bj], a, 0, 0, 0);
+                        acc[E >> 2] = a;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        if constexpr (kTwoLevel) {
+            if ((st + 1) % kFlush == 0) {
+#pragma unroll
+                for (int e = 0; e < kSlots; ++e) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) { acc2[e][r] += acc[e][r]; acc[e][r] = 0.f; }
+                }
+            }
+        }
+    }
+
+    // Partial second moment of this chunk: [chunk][block][reg][lane].
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi) {
+#pragma unroll
+        for (int bj = bi; bj < 8; ++bj) {
+            const int E = static_block(bi, bj);
+            if ((E & 3) != wave || bj >= nb) continue;
+            float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) dst[r * 64] = kTwoLevel ? acc2[(E >> 2) % kSlots2][r] + acc[E >> 2][r] : acc[E >> 2][r];
+        }
+    }
+
+    // Band sums: the four waves saw different pixels of the same bands.
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int b = slot_band<VEC>(lane, s);
+        if (b < 256) red[wave][b] = sums[s];
+    }
+    __syncthreads();
+    for (int b = tid; b < mpad; b += kThreads) {
+        const double t = ((red[0][b] + red[1][b]) + red[2][b]) + red[3][b];
+        partSum[c * mpad + b] = t;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void cov_finalize_kernel(
+    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk,
+    int64_t nchunks, int nb, int nblk, int mpad, const float *__restrict__ partS,
+    const double *__restrict__ partSum, float *__restrict__ C, float *__restrict__ mean)
+{
+    constexpr int kBatch = 32;
+    __shared__ double mu[64];
+    __shared__ float shv[kBatch][64];
+    __shared__ double smv[kBatch][64];
+
+    const int e = blockIdx.x;
+    int bi = 0, rem = e;
+    while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
+    const int bj = bi + rem;
+    const int tid = threadIdx.x;
+    const int r = tid >> 6, lane = tid & 63;
+    const int il = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);   // MFMA 32x32 result layout
+    const int jl = lane & 31;
+
+    if (tid < 64) {
+        const int b = tid < 32 ? 32 * bi + tid : 32 * bj + (tid - 32);
+        double a = 0.0;
+        if (b < m && !centered) {
+            for (int64_t w = 0; w < nchunks; ++w) {
+                const int64_t p0 = w * chunk;
+                const int64_t nw = (p0 + chunk < n ? p0 + chunk : n) - p0;
+                a += (double)nw * (double)load_elem(Y + p0 * ld + b) + partSum[w * mpad + b];
+            }
+        }
+        mu[tid] = (b < m && !centered) ? a / (double)n : 0.0;
+    }
+    __syncthreads();
+
+    double acc = 0.0;
+    for (int64_t w0 = 0; w0 < nchunks; w0 += kBatch) {
+        const int nbatch = (int)((nchunks - w0) < kBatch ? (nchunks - w0) : kBatch);
+        for (int t = tid; t < kBatch * 64; t += 1024) {
+            const int cc = t >> 6, q = t & 63;
+            const int b = q < 32 ? 32 * bi + q : 32 * bj + (q - 32);
+            float sh = 0.f;
+            double sm = 0.0;
+            if (cc < nbatch && b < mpad) {
+                const int64_t w = w0 + cc;
+                sm = partSum[w * mpad + b];
+                if (!centered && b < m) sh = load_elem(Y + (w * chunk) * ld + b);
+            }
+            shv[cc][q] = sh;
+            smv[cc][q] = sm;
+        }
+        __syncthreads();
+        for (int cc = 0; cc < nbatch; ++cc) {
+            const int64_t w = w0 + cc;
+            const int64_t p0 = w * chunk;
+            const double nw = (double)((p0 + chunk < n ? p0 + chunk : n) - p0);
+            const double ei = (double)shv[cc][il] - mu[il];
+            const double ej = (double)shv[cc][32 + jl] - mu[32 + jl];
+            const double s = (double)partS[(w * nblk + e) * 1024 + tid];
+            acc += s + smv[cc][il] * ej + ei * smv[cc][32 + jl] + nw * ei * ej;
+        }
+        __syncthreads();
+    }
+
+    const int i = 32 * bi + il, j = 32 * bj + jl;
+    if (i < m && j < m && !(bi == bj && i > j)) {
+        const float val = (float)(acc / (double)(n - 1));
+        C[(int64_t)i * m + j] = val;
+        C[(int64_t)j * m + i] = val;
+    }
+    if (mean && !centered && bi == bj && tid < 32 && 32 * bi + tid < m) mean[32 * bi + tid] = (float)mu[tid];
+}
+
+template <typename T, int VEC>
+hipError_t launch_partial_t(const T *Y, int64_t n, int m, int64_t ld, int centered, int mode,
+                            const CovPlan &p, float *partS, double *partSum, hipStream_t st)
+{
+    dim3 grid((unsigned)p.nchunks), block(kThreads);
+    switch (mode) {
+    case MODE_F32:
+        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_F32>), grid, block, 0, st, Y, n, m, ld,
+                           centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum);
+        break;
+    case MODE_BF16X3:
+        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_BF16X3>), grid, block, 0, st, Y, n, m,
+                           ld, centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum);
+        break;
+    default:
+        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_BF16X4>), grid, block, 0, st, Y, n, m,
+                           ld, centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+CovPlan cov_plan(int64_t n, int m)
+{
+    CovPlan p;
+    int64_t target = (n + kCovTargetChunks - 1) / kCovTargetChunks;
+    target = (target + KT - 1) / KT * KT;
+    if (target < KT) target = KT;
+    if (target > kCovMaxChunk) target = kCovMaxChunk;
+    p.chunk = target;
+    p.nchunks = (n + p.chunk - 1) / p.chunk;
+    p.mpad = round_up(m, 32);
+    p.nb = p.mpad / 32;
+    p.nblk = p.nb * (p.nb + 1) / 2;
+    p.bytes_S = (size_t)p.nchunks * p.nblk * 1024 * sizeof(float);
+    p.bytes_sum = (size_t)p.nchunks * p.mpad * sizeof(double);
+    return p;
+}
+
+hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
+                              int mode, const CovPlan &plan, float *partS, double *partSum,
+                              hipStream_t st)
+{
+    const bool v4 = vec4_ok(Y, dt, ld);
+    if (dt == PCA_IN_F32) {
+        const float *y = static_cast<const float *>(Y);
+        return v4 ? launch_partial_t<float, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, st)
+                  : launch_partial_t<float, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, st);
+    }
+    const uint16_t *y = static_cast<const uint16_t *>(Y);
+    return v4 ? launch_partial_t<uint16_t, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, st)
+              : launch_partial_t<uint16_t, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, st);
+}
+
+hipError_t launch_cov_finalize(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
+                               const CovPlan &plan, const float *partS, const double *partSum,
+                               float *C, float *mean, hipStream_t st)
+{
+    dim3 grid((unsigned)plan.nblk), block(1024);
+    if (dt == PCA_IN_F32)
+        hipLaunchKernelGGL(cov_finalize_kernel<float>, grid, block, 0, st,
+                           static_cast<const float *>(Y), n, m, ld, centered, plan.chunk,
+                           plan.nchunks, plan.nb, plan.nblk, plan.mpad, partS, partSum, C, mean);
+    else
+        hipLaunchKernelGGL(cov_finalize_kernel<uint16_t>, grid, block, 0, st,
+                           static_cast<const uint16_t *>(Y), n, m, ld, centered, plan.chunk,
+                           plan.nchunks, plan.nb, plan.nblk, plan.mpad, partS, partSum, C, mean);
+    return hipGetLastError();
+}
+
+}  // namespace pca

@@ -10,6 +10,7 @@ from .cubes import (  # noqa: F401
     CONFIGS,
     batch_shapes,
     endmember_spectra,
+    haar_orthogonal,
     make_batch,
     make_config,
     mixture_cube,

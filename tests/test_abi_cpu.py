@@ -1,0 +1,82 @@
+"""The C ABI library loads on a machine without a GPU, exports every entry
+point that include/pca.h declares, and rejects bad arguments before touching
+the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pca.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2403_18321_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2403_18321_amd import build_lib
+        build_lib.build(verbose=False)
+    return L
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pca_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(lib):
+    names = declared_functions()
+    assert "pca_covariance" in names and "pca_jacobi_eigh" in names
+    so = ctypes.CDLL(lib.LIB_PATH)
+    for name in names:
+        assert hasattr(so, name), f"{name} declared in pca.h but not exported"
+    assert set(names) <= set(lib.EXPORTS) | {"pca_backward"}
+
+
+def test_status_strings(lib):
+    so = lib.library()
+    for code in range(5):
+        assert so.pca_status_string(code).startswith(b"PCA_")
+
+
+def test_workspace_sizes(lib):
+    L = lib
+    a = L.pca_workspace_size(L.PCA_OP_COVARIANCE, 1 << 20, 224, mode=L.PCA_COV_BF16X3)
+    b = L.pca_workspace_size(L.PCA_OP_COVARIANCE, 1 << 16, 224)
+    assert a >= b > 0
+    j = L.pca_workspace_size(L.PCA_OP_JACOBI, 2, 224, max_sweeps=30)
+    assert j >= 30 * 223 * 112 * 8
+    assert L.pca_workspace_size(L.PCA_OP_PROJECT, 100, 10) == 0
+    with pytest.raises(L.PCAError):
+        L.pca_workspace_size(L.PCA_OP_COVARIANCE, 100, 257)
+    with pytest.raises(L.PCAError):
+        L.pca_workspace_size(L.PCA_OP_COVARIANCE, 1, 16)
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    so = lib.library()
+    ARG = lib.PCA_ERR_ARG
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(4096)     # never dereferenced: checks fail first
+    # NULL cube.
+    assert so.pca_covariance(null, 0, 100, 8, 8, 0, null, 0, fake, fake, 1 << 20, null) == ARG
+    # Too many bands, too few pixels, ld < bands, bad mode, bad dtype.
+    assert so.pca_covariance(fake, 0, 100, 257, 257, 0, null, 0, fake, fake, 1 << 20, null) == ARG
+    assert so.pca_covariance(fake, 0, 1, 8, 8, 0, null, 0, fake, fake, 1 << 20, null) == ARG
+    assert so.pca_covariance(fake, 0, 100, 8, 7, 0, null, 0, fake, fake, 1 << 20, null) == ARG
+    assert so.pca_covariance(fake, 0, 100, 8, 8, 0, null, 7, fake, fake, 1 << 20, null) == ARG
+    assert so.pca_covariance(fake, 5, 100, 8, 8, 0, null, 0, fake, fake, 1 << 20, null) == ARG
+    # Workspace too small.
+    assert so.pca_covariance(fake, 0, 100000, 64, 64, 0, null, 0, fake, fake, 256,
+                             null) == lib.PCA_ERR_WORKSPACE
+    # Jacobi: negative tolerance, too many bands, misaligned workspace.
+    assert so.pca_jacobi_eigh(fake, 8, -1.0, 10, 1, fake, fake, null, fake, 1 << 20, null) == ARG
+    assert so.pca_jacobi_eigh(fake, 300, 1e-6, 10, 1, fake, fake, null, fake, 1 << 20, null) == ARG
+    assert so.pca_jacobi_eigh(fake, 8, 1e-6, 10, 1, fake, fake, null, ctypes.c_void_p(4100), 1 << 20,
+                              null) == ARG
+    # Projection: k out of range.
+    assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 0, fake, null) == ARG
+    assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 9, fake, null) == ARG
