@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""End-to-end PCA throughput on one MI355X.
+
+Workload: the 224-band radiance cube, 1024 x 1024 pixels (uint16 counts with
+Poisson-like noise from the seeded generator, converted to float32 before
+timing), k = 10 components. One step is the whole hot path on one cube:
+fused centring + covariance, cyclic Jacobi eigendecomposition (with
+eigenvector replay, sort and sign fix) and projection. The cube is resident in
+HBM before timing starts.
+
+The metric is Mpixel*band/s = pixels * bands * steps / time / 1e6, measured for
+the plain float32 covariance and for the split-bfloat16 forms; `value` is the
+fastest form whose eigenvalue error against the FP64 oracle is <= 1e-5
+(normwise). Also reported: per-stage times from HIP events on the stream the
+kernels run on, the roofline of the dominant kernel, and the FP64 oracle timed
+on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "end-to-end PCA Mpixel·band/s; split-BF16 vs FP32 at ≤1e-5 eigval error"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, datasheet
+MFMA_F32_PEAK_TFS = 157.3      # dense FP32 matrix
+MFMA_BF16_PEAK_TFS = 2500.0    # dense BF16 matrix
+EIG_TOL = 1e-5
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_pipeline(P, torch, pipe, Yd, steps, warmup):
+    for _ in range(warmup):
+        pipe.forward(Yd)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        pipe.forward(Yd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def time_stages(P, torch, pipe, Yd, steps):
+    """Per-stage times from events recorded between the three C-ABI calls."""
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for s in range(steps):
+        ev[s][0].record(stream)
+        pipe.covariance(Yd)
+        ev[s][1].record(stream)
+        pipe.eigh()
+        ev[s][2].record(stream)
+        pipe.project(Yd)
+        ev[s][3].record(stream)
+    torch.cuda.synchronize()
+    names = ("covariance", "jacobi_eigh", "project")
+    out = {}
+    for i, nm in enumerate(names):
+        out[nm] = statistics.mean(ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(steps))
+    return out
+
+
+def cpu_baseline(oracle, Y, k, budget_s=12.0, max_runs=5):
+    """The FP64 oracle on the same cube, repeated until ~budget_s of work."""
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    times = []
+    t_all = time.perf_counter()
+    while len(times) < max_runs and (time.perf_counter() - t_all) < budget_s:
+        t0 = time.perf_counter()
+        oracle.pca(Y, k)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    n, m = Y.shape
+    return dict(value=round(n * m / med / 1e6, 3), unit="Mpixel·band/s", cores=int(threads), kind="oracle",
+                sample=f"full cube {n} px x {m} bands, k={k}, float64 mean/covariance/row-cyclic Jacobi/"
+                       f"projection; median of {len(times)} runs ({med:.2f} s each)")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--modes", default="f32,bf16x3,bf16x4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the pixel-sharded design is described in the design notes).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2403_18321_amd as P
+    import synth
+
+    P.library()  # fail loudly if the HIP library is missing
+    log("generating the 224-band cube ...")
+    d = synth.make_config("c3")
+    k = d["k"]
+    Yu = d["Y_u16"]
+    n, m = Yu.shape
+    Yd = torch.from_numpy(d["Y"]).cuda()
+    torch.cuda.synchronize()
+
+    ref = None
+    oracle = None
+    if not args.no_accuracy or not args.no_cpu_baseline:
+        import oracle as _oracle
+        oracle = _oracle
+    if not args.no_accuracy:
+        log("FP64 oracle for the accuracy report ...")
+        ref = oracle.pca(Yu, k)
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity_utils import report
+
+    modes = {}
+    for mode in args.modes.split(","):
+        pipe = P.PCAPipeline(n, m, k, mode)
+        ms, wall = time_pipeline(P, torch, pipe, Yd, args.steps, args.warmup)
+        stages = time_stages(P, torch, pipe, Yd, max(3, min(args.steps, 10)))
+        info = pipe.forward(Yd).read_info()
+        rec = dict(ms_per_step=round(ms, 4), value=round(n * m / (ms * 1e-3) / 1e6, 1),
+                   wall_s=round(wall, 3), stages_ms={kk: round(v, 4) for kk, v in stages.items()},
+                   sweeps=info["sweeps"], steps_jacobi=info["steps"], off_rel=info["off_rel"],
+                   converged=info["converged"])
+        if ref is not None:
+            r = report(pipe.eigvals.cpu().numpy(), pipe.V.cpu().numpy(), pipe.Q.cpu().numpy(), ref, k)
+            rec.update(eig_err=r["eig"], angle_err=r["angle"], proj_err=r["proj"])
+        modes[mode] = rec
+        log(mode, json.dumps(rec))
+
+    ok = [mm for mm, r in modes.items() if r.get("eig_err", 0.0) <= EIG_TOL]
+    best = min(ok or list(modes), key=lambda mm: modes[mm]["ms_per_step"])
+    br = modes[best]
+
+    # Roofline of the dominant kernel of the best form.
+    stages = br["stages_ms"]
+    dom = max(stages, key=stages.get)
+    t = stages[dom] * 1e-3
+    if dom == "covariance":
+        if best == "f32":
+            flops = n * m * (m + 1)
+            achieved = flops / t / 1e12
+            roof = dict(bound="mfma", achieved=round(achieved, 2), peak=MFMA_F32_PEAK_TFS, unit="TFLOP/s")
+        else:
+            bytes_ = n * m * 4
+            achieved = bytes_ / t / 1e9
+            roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s")
+    elif dom == "project":
+        bytes_ = n * m * 4 + n * k * 4
+        achieved = bytes_ / t / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s")
+    else:
+        # One workgroup on one CU: the bound is that CU's float32 FMA rate
+        # without packed instructions, 64 lanes x 2 flop x 2.4 GHz = 307.2
+        # GFLOP/s. Algorithmic work: 24 flops per off-diagonal 2x2 block
+        # (both sides of the rotation), (M/2)(M/2 - 1)/2 blocks per step.
+        me = m + (m & 1)
+        pairs = me // 2
+        flops = br["steps_jacobi"] * 24 * pairs * (pairs - 1) // 2
+        achieved = flops / t / 1e9
+        roof = dict(bound="alu", achieved=round(achieved, 1), peak=307.2, unit="GFLOP/s")
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["kernel"] = dom
+    roof["traffic"] = None
+
+    out = dict(metric=METRIC, value=br["value"], unit="Mpixel·band/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=br["ms_per_step"], higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype={"f32": "f32", "bf16x3": "bf16", "bf16x4": "bf16"}[best], data="synthetic",
+               config=dict(workload="224-band radiance cube, 1024x1024 px (uint16 counts -> float32), k=10",
+                           n_pixels=n, n_bands=m, k=k, cov_mode=best),
+               roofline=roof, modes=modes)
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(oracle, Yu, k)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
