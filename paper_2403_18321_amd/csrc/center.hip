@@ -26,14 +26,15 @@ __global__ __launch_bounds__(kThreads) void center_sums_kernel(const T *__restri
     const int64_t pbeg = c * chunk;
     const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
-    float v[8][4];
+    Group<T, VEC> v;
     for (int64_t g = pbeg + 8 * wave; g < pend; g += 32) {
-        load_group<T, VEC>(Y, ld, g, pend, m, lane, v);
+        v.load(Y, ld, g, pend, m, lane);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
+            const bool okb = slot_band<VEC>(lane, s) < m;
             double t = 0.0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) t += (double)v[i][s];
+            for (int i = 0; i < 8; ++i) t += (okb && g + i < pend) ? (double)v.get(i, s) : 0.0;
             sums[s] += t;
         }
     }
@@ -100,7 +101,7 @@ hipError_t launch_center_t(const T *Y, int64_t n, int m, int64_t ld, float *mean
 hipError_t launch_center(const void *Y, int dt, int64_t n, int m, int64_t ld, float *mean, float *X,
                          int64_t ldx, const CovPlan &plan, double *partSum, double *mean64, hipStream_t st)
 {
-    const bool v4 = vec4_ok(Y, dt, ld);
+    const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32)
         return launch_center_t(static_cast<const float *>(Y), n, m, ld, mean, X, ldx, plan, partSum, mean64, st, v4);
     return launch_center_t(static_cast<const uint16_t *>(Y), n, m, ld, mean, X, ldx, plan, partSum, mean64, st, v4);

@@ -19,24 +19,6 @@ __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m *
 __device__ inline float load_elem(const float *p) { return *p; }
 __device__ inline float load_elem(const uint16_t *p) { return (float)(*p); }
 
-// Round-robin tournament used for the parallel Jacobi steps (n even). Player 0
-// stays at position 0; the other n-1 players turn by one position per step.
-// Position j of step s holds player 1 + ((j - 1 + s) mod (n - 1)) (j >= 1).
-// Pair k of step s is (position k, position n-1-k). Returned with a < b.
-__device__ inline void rr_pair(int n, int step, int k, int &a, int &b)
-{
-    const int m = n - 1;
-    auto player = [&](int pos) -> int {
-        if (pos == 0) return 0;
-        int v = pos - 1 + step;
-        v %= m;
-        return 1 + v;
-    };
-    int x = player(k), y = player(n - 1 - k);
-    a = x < y ? x : y;
-    b = x < y ? y : x;
-}
-
 // Wave-wide sum of a double (butterfly over the 64 lanes).
 __device__ inline double wave_sum(double v)
 {

@@ -50,7 +50,7 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 template <typename T, int VEC, int MODE>
 __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
-    int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum)
+    int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
 {
     constexpr int kF32Max = KT * (256 + 32);
     constexpr int kBfMax = 256 * kBfPitch;
@@ -95,11 +95,18 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
         for (int r = 0; r < 16; ++r) acc2[e][r] = 0.f;
     }
 
-    float v[8][4];
-    load_group<T, VEC>(Y, ld, pbeg + 8 * wave, pend, m, lane, v);
-
+    // Register prefetch of PREF stages ahead (float32 mode needs its registers
+    // for the two-level accumulators).
+    constexpr int PREF = MODE == MODE_F32 ? 1 : 2;
     const int64_t nst = (pend - pbeg + KT - 1) / KT;
-    for (int64_t st = 0; st < nst; ++st) {
+    Group<T, VEC> ga, gb;
+    ga.load(Y, ld, pbeg + 8 * wave, pend, m, lane);
+    if (PREF == 2 && nst > 1) gb.load(Y, ld, pbeg + KT + 8 * wave, pend, m, lane);
+    bool bok[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) bok[s] = slot_band<VEC>(lane, s) < m;
+
+    auto stage = [&](Group<T, VEC> &v, int64_t st) {
         const int64_t g0 = pbeg + st * KT + 8 * wave;  // first pixel of this wave's group
         const int64_t nval64 = pend - g0;
         const int nval = nval64 < 0 ? 0 : (nval64 > 8 ? 8 : (int)nval64);
@@ -110,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
             const int b = slot_band<VEC>(lane, s);
             float x[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) x[i] = (i < nval) ? v[i][s] - shift[s] : 0.f;
+            for (int i = 0; i < 8; ++i) x[i] = (i < nval && bok[s]) ? v.get(i, s) - shift[s] : 0.f;
             double ts = 0.0;
 #pragma unroll
             for (int i = 0; i < 8; ++i) ts += (double)x[i];
@@ -144,14 +151,14 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
                 for (int i = 0; i < 8; ++i) {
                     f32x4 q;
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) q[s] = (i < nval) ? v[i][s] - shift[s] : 0.f;
+                    for (int s = 0; s < 4; ++s) q[s] = (i < nval && bok[s]) ? v.get(i, s) - shift[s] : 0.f;
                     *reinterpret_cast<f32x4 *>(&tileF[(8 * wave + i) * pf + b]) = q;
                 }
             }
         }
 
-        // Prefetch the next stage while this one is multiplied.
-        if (st + 1 < nst) load_group<T, VEC>(Y, ld, g0 + KT, pend, m, lane, v);
+        // Prefetch a later stage while this one is multiplied.
+        if (st + PREF < nst) v.load(Y, ld, g0 + PREF * KT, pend, m, lane);
         __syncthreads();
 
         if constexpr (MODE == MODE_F32) {
@@ -216,6 +223,11 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
                 }
             }
         }
+    };
+
+    for (int64_t st = 0; st < nst; st += PREF) {
+        stage(ga, st);
+        if (PREF == 2 && st + 1 < nst) stage(gb, st + 1);
     }
 
     // Partial second moment of this chunk: [chunk][block][reg][lane].
@@ -242,16 +254,21 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
         const double t = ((red[0][b] + red[1][b]) + red[2][b]) + red[3][b];
         partSum[c * mpad + b] = t;
     }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int b = slot_band<VEC>(lane, s);
+        if (wave == 0 && b < mpad) partShift[c * mpad + b] = shift[s];
+    }
 }
 
-template <typename T>
 __global__ __launch_bounds__(1024) void cov_finalize_kernel(
-    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk,
-    int64_t nchunks, int nb, int nblk, int mpad, const float *__restrict__ partS,
-    const double *__restrict__ partSum, float *__restrict__ C, float *__restrict__ mean)
+    int64_t n, int m, int centered, int64_t chunk, int64_t nchunks, int nb, int nblk, int mpad,
+    const float *__restrict__ partS, const double *__restrict__ partSum, const float *__restrict__ partShift,
+    float *__restrict__ C, float *__restrict__ mean)
 {
     constexpr int kBatch = 32;
     __shared__ double mu[64];
+    __shared__ double mred[16][64];
     __shared__ float shv[kBatch][64];
     __shared__ double smv[kBatch][64];
 
@@ -263,18 +280,26 @@ __global__ __launch_bounds__(1024) void cov_finalize_kernel(
     const int r = tid >> 6, lane = tid & 63;
     const int il = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);   // MFMA 32x32 result layout
     const int jl = lane & 31;
+    auto band = [&](int q) { return q < 32 ? 32 * bi + q : 32 * bj + (q - 32); };
+    auto pixels = [&](int64_t w) { return (double)((w * chunk + chunk < n ? w * chunk + chunk : n) - w * chunk); };
 
-    if (tid < 64) {
-        const int b = tid < 32 ? 32 * bi + tid : 32 * bj + (tid - 32);
+    // Band means of this block's 64 bands in float64: wave w adds a contiguous
+    // range of chunks, then the 16 wave sums are added in order.
+    {
+        const int b = band(lane);
+        const int64_t w0 = (int64_t)r * nchunks / 16, w1 = (int64_t)(r + 1) * nchunks / 16;
         double a = 0.0;
         if (b < m && !centered) {
-            for (int64_t w = 0; w < nchunks; ++w) {
-                const int64_t p0 = w * chunk;
-                const int64_t nw = (p0 + chunk < n ? p0 + chunk : n) - p0;
-                a += (double)nw * (double)load_elem(Y + p0 * ld + b) + partSum[w * mpad + b];
-            }
+            for (int64_t w = w0; w < w1; ++w)
+                a += pixels(w) * (double)partShift[w * mpad + b] + partSum[w * mpad + b];
         }
-        mu[tid] = (b < m && !centered) ? a / (double)n : 0.0;
+        mred[r][lane] = a;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double a = 0.0;
+        for (int w = 0; w < 16; ++w) a += mred[w][tid];
+        mu[tid] = (band(tid) < m && !centered) ? a / (double)n : 0.0;
     }
     __syncthreads();
 
@@ -283,26 +308,30 @@ __global__ __launch_bounds__(1024) void cov_finalize_kernel(
         const int nbatch = (int)((nchunks - w0) < kBatch ? (nchunks - w0) : kBatch);
         for (int t = tid; t < kBatch * 64; t += 1024) {
             const int cc = t >> 6, q = t & 63;
-            const int b = q < 32 ? 32 * bi + q : 32 * bj + (q - 32);
+            const int b = band(q);
             float sh = 0.f;
             double sm = 0.0;
             if (cc < nbatch && b < mpad) {
                 const int64_t w = w0 + cc;
                 sm = partSum[w * mpad + b];
-                if (!centered && b < m) sh = load_elem(Y + (w * chunk) * ld + b);
+                if (!centered) sh = partShift[w * mpad + b];
             }
             shv[cc][q] = sh;
             smv[cc][q] = sm;
         }
+        float sv[kBatch];
+#pragma unroll
+        for (int cc = 0; cc < kBatch; ++cc)
+            sv[cc] = cc < nbatch ? partS[((w0 + cc) * nblk + e) * 1024 + tid] : 0.f;
         __syncthreads();
-        for (int cc = 0; cc < nbatch; ++cc) {
-            const int64_t w = w0 + cc;
-            const int64_t p0 = w * chunk;
-            const double nw = (double)((p0 + chunk < n ? p0 + chunk : n) - p0);
-            const double ei = (double)shv[cc][il] - mu[il];
-            const double ej = (double)shv[cc][32 + jl] - mu[32 + jl];
-            const double s = (double)partS[(w * nblk + e) * 1024 + tid];
-            acc += s + smv[cc][il] * ej + ei * smv[cc][32 + jl] + nw * ei * ej;
+#pragma unroll
+        for (int cc = 0; cc < kBatch; ++cc) {
+            if (cc < nbatch) {
+                const double nw = pixels(w0 + cc);
+                const double ei = (double)shv[cc][il] - mu[il];
+                const double ej = (double)shv[cc][32 + jl] - mu[32 + jl];
+                acc += (double)sv[cc] + smv[cc][il] * ej + ei * smv[cc][32 + jl] + nw * ei * ej;
+            }
         }
         __syncthreads();
     }
@@ -318,21 +347,21 @@ __global__ __launch_bounds__(1024) void cov_finalize_kernel(
 
 template <typename T, int VEC>
 hipError_t launch_partial_t(const T *Y, int64_t n, int m, int64_t ld, int centered, int mode,
-                            const CovPlan &p, float *partS, double *partSum, hipStream_t st)
+                            const CovPlan &p, float *partS, double *partSum, float *partShift, hipStream_t st)
 {
     dim3 grid((unsigned)p.nchunks), block(kThreads);
     switch (mode) {
     case MODE_F32:
         hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_F32>), grid, block, 0, st, Y, n, m, ld,
-                           centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum);
+                           centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift);
         break;
     case MODE_BF16X3:
         hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_BF16X3>), grid, block, 0, st, Y, n, m,
-                           ld, centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum);
+                           ld, centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift);
         break;
     default:
         hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_BF16X4>), grid, block, 0, st, Y, n, m,
-                           ld, centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum);
+                           ld, centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift);
         break;
     }
     return hipGetLastError();
@@ -354,37 +383,30 @@ CovPlan cov_plan(int64_t n, int m)
     p.nblk = p.nb * (p.nb + 1) / 2;
     p.bytes_S = (size_t)p.nchunks * p.nblk * 1024 * sizeof(float);
     p.bytes_sum = (size_t)p.nchunks * p.mpad * sizeof(double);
+    p.bytes_shift = (size_t)p.nchunks * p.mpad * sizeof(float);
     return p;
 }
 
 hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
                               int mode, const CovPlan &plan, float *partS, double *partSum,
-                              hipStream_t st)
+                              float *partShift, hipStream_t st)
 {
-    const bool v4 = vec4_ok(Y, dt, ld);
+    const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32) {
         const float *y = static_cast<const float *>(Y);
-        return v4 ? launch_partial_t<float, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, st)
-                  : launch_partial_t<float, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, st);
+        return v4 ? launch_partial_t<float, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st)
+                  : launch_partial_t<float, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st);
     }
     const uint16_t *y = static_cast<const uint16_t *>(Y);
-    return v4 ? launch_partial_t<uint16_t, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, st)
-              : launch_partial_t<uint16_t, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, st);
+    return v4 ? launch_partial_t<uint16_t, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st)
+              : launch_partial_t<uint16_t, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st);
 }
 
-hipError_t launch_cov_finalize(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
-                               const CovPlan &plan, const float *partS, const double *partSum,
-                               float *C, float *mean, hipStream_t st)
+hipError_t launch_cov_finalize(int64_t n, int m, int centered, const CovPlan &plan, const float *partS,
+                               const double *partSum, const float *partShift, float *C, float *mean, hipStream_t st)
 {
-    dim3 grid((unsigned)plan.nblk), block(1024);
-    if (dt == PCA_IN_F32)
-        hipLaunchKernelGGL(cov_finalize_kernel<float>, grid, block, 0, st,
-                           static_cast<const float *>(Y), n, m, ld, centered, plan.chunk,
-                           plan.nchunks, plan.nb, plan.nblk, plan.mpad, partS, partSum, C, mean);
-    else
-        hipLaunchKernelGGL(cov_finalize_kernel<uint16_t>, grid, block, 0, st,
-                           static_cast<const uint16_t *>(Y), n, m, ld, centered, plan.chunk,
-                           plan.nchunks, plan.nb, plan.nblk, plan.mpad, partS, partSum, C, mean);
+    hipLaunchKernelGGL(cov_finalize_kernel, dim3((unsigned)plan.nblk), dim3(1024), 0, st, n, m, centered, plan.chunk,
+                       plan.nchunks, plan.nb, plan.nblk, plan.mpad, partS, partSum, partShift, C, mean);
     return hipGetLastError();
 }
 

@@ -24,15 +24,16 @@ struct CovPlan {
     int nblk;          // upper-triangle blocks nb (nb + 1) / 2
     size_t bytes_S;    // partial second moments, float32
     size_t bytes_sum;  // partial sums, float64
+    size_t bytes_shift;  // per-chunk shifts, float32
 };
 CovPlan cov_plan(int64_t n, int m);
 
 hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
                               int mode, const CovPlan &plan, float *partS, double *partSum,
-                              hipStream_t st);
-hipError_t launch_cov_finalize(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
-                               const CovPlan &plan, const float *partS, const double *partSum,
-                               float *C, float *mean, hipStream_t st);
+                              float *partShift, hipStream_t st);
+hipError_t launch_cov_finalize(int64_t n, int m, int centered, const CovPlan &plan, const float *partS,
+                               const double *partSum, const float *partShift, float *C, float *mean,
+                               hipStream_t st);
 
 // ---- centring --------------------------------------------------------------
 hipError_t launch_center(const void *Y, int dt, int64_t n, int m, int64_t ld, float *mean,

@@ -1,11 +1,13 @@
 // Projection of every pixel onto the first k eigenvectors (Algorithm 1, lines
 // 5-6): Q'[p, i] = sum_b (Y[p, b] - mu_b) V[b, i], i < k.
 //
-// A workgroup stages 64 pixels x all bands in LDS (coalesced reads, the mean
-// subtracted on the way in: the centred cube is never written to HBM), then
-// each wave multiplies its 16 pixels by V[:, 16g .. 16g+15] with
-// v_mfma_f32_16x16x4_f32, K = bands. The eigenvector block lives in
-// registers for the whole workgroup. The cube is read once per group of 16
+// Persistent workgroups (two per CU) walk over tiles of 64 pixels. A tile is
+// read from HBM with coalesced row loads, centred on the way into LDS (the
+// centred cube is never written back), and multiplied by the block
+// V[:, 16g .. 16g+15] with v_mfma_f32_16x16x4_f32 (K = bands), each wave
+// taking 16 pixels. The eigenvector block stays in registers for the
+// workgroup's lifetime, and the next tile's loads are in flight while the
+// current tile is multiplied. The cube is read once per group of 16
 // components (once for k <= 16).
 #include "common.hpp"
 #include "kernels.hpp"
@@ -16,8 +18,9 @@ namespace pca {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kTP = 64;                  // pixels per workgroup (4 waves x 16)
+constexpr int kTP = 64;                  // pixels per tile (4 waves x 16)
 constexpr int kMaxKSteps = 64;           // 256 bands / 4
+constexpr int kWGPerCU = 2;
 
 // Tile pitch (floats): a multiple of 4 with pitch/4 odd, so the 16 pixels x 4
 // bands read by one MFMA operand load hit 64 distinct LDS banks.
@@ -36,7 +39,7 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__
     const int pitch = proj_pitch(m4);
     const int ksteps = m4 / 4;
     const int g = blockIdx.y;
-    const int64_t p0 = (int64_t)blockIdx.x * kTP;
+    const int64_t ntiles = (n + kTP - 1) / kTP;
 
     for (int b = tid; b < 256; b += kThreads) mu[b] = (mean && b < m) ? mean[b] : 0.f;
 
@@ -52,59 +55,91 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__
     }
     __syncthreads();
 
-    // Stage the centred pixels: wave w loads groups w and w + 4 (8 pixels each).
+    // Wave w loads pixel groups w and w + 4 (8 pixels each) of a tile.
+    Group<T, VEC> v0, v1;
+    int64_t t = blockIdx.x;
+    if (t < ntiles) {
+        v0.load(Y, ld, t * kTP + 8 * wave, n, m, lane);
+        v1.load(Y, ld, t * kTP + 8 * (wave + 4), n, m, lane);
+    }
+    const float *arow = &tile[(16 * wave + (lane & 15)) * pitch + (lane >> 4)];
+    for (; t < ntiles; t += gridDim.x) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int grp = wave + 4 * h;
-        float v[8][4];
-        load_group<T, VEC>(Y, ld, p0 + 8 * grp, n, m, lane, v);
-        if constexpr (VEC == 4) {
-            const int b = 4 * lane;
-            if (b < m4) {
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    f32x4 q;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) q[s] = (b + s < m) ? v[i][s] - mu[b + s] : 0.f;
-                    *reinterpret_cast<f32x4 *>(&tile[(8 * grp + i) * pitch + b]) = q;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int b = lane + 64 * s;
+        for (int h = 0; h < 2; ++h) {
+            const int grp = wave + 4 * h;
+            const Group<T, VEC> &v = h == 0 ? v0 : v1;
+            const int64_t pg = t * kTP + 8 * grp;
+            if constexpr (VEC == 4) {
+                const int b = 4 * lane;
                 if (b < m4) {
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) tile[(8 * grp + i) * pitch + b] = (b < m) ? v[i][s] - mu[b] : 0.f;
+                    for (int i = 0; i < 8; ++i) {
+                        f32x4 q;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) q[s] = (b + s < m && pg + i < n) ? v.get(i, s) - mu[b + s] : 0.f;
+                        *reinterpret_cast<f32x4 *>(&tile[(8 * grp + i) * pitch + b]) = q;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int b = lane + 64 * s;
+                    if (b < m4) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            tile[(8 * grp + i) * pitch + b] = (b < m && pg + i < n) ? v.get(i, s) - mu[b] : 0.f;
+                    }
                 }
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const float *arow = &tile[(16 * wave + (lane & 15)) * pitch + (lane >> 4)];
-#pragma unroll
-    for (int s = 0; s < kMaxKSteps; ++s) {
-        if (s < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[4 * s], bv[s], acc, 0, 0, 0);
-    }
-
-    // 16x16 result layout: lane holds rows 4 (lane/16) + r, column lane % 16.
-    const int o = 16 * g + (lane & 15);
-    if (o < k) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t p = p0 + 16 * wave + 4 * (lane >> 4) + r;
-            if (p < n) Q[p * k + o] = acc[r];
+        // Next tile's loads overlap this tile's products.
+        const int64_t tn = t + gridDim.x;
+        if (tn < ntiles) {
+            v0.load(Y, ld, tn * kTP + 8 * wave, n, m, lane);
+            v1.load(Y, ld, tn * kTP + 8 * (wave + 4), n, m, lane);
         }
+
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < kMaxKSteps; ++s) {
+            if (s < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[4 * s], bv[s], acc, 0, 0, 0);
+        }
+
+        // 16x16 result layout: lane holds rows 4 (lane/16) + r, column lane % 16.
+        const int o = 16 * g + (lane & 15);
+        if (o < k) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t p = t * kTP + 16 * wave + 4 * (lane >> 4) + r;
+                if (p < n) Q[p * k + o] = acc[r];
+            }
+        }
+        __syncthreads();
     }
+}
+
+int num_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
 }
 
 template <typename T>
 hipError_t launch_t(const T *Y, int64_t n, int m, int64_t ld, const float *mean, const float *V, int k,
                     float *Q, hipStream_t st, bool v4)
 {
-    dim3 grid((unsigned)((n + kTP - 1) / kTP), (unsigned)((k + 15) / 16)), block(kThreads);
+    const int64_t ntiles = (n + kTP - 1) / kTP;
+    int64_t gx = (int64_t)num_cus() * kWGPerCU;
+    if (gx > ntiles) gx = ntiles;
+    dim3 grid((unsigned)gx, (unsigned)((k + 15) / 16)), block(kThreads);
     if (v4)
         hipLaunchKernelGGL((project_kernel<T, 4>), grid, block, 0, st, Y, n, m, ld, mean, V, k, Q);
     else
@@ -117,7 +152,7 @@ hipError_t launch_t(const T *Y, int64_t n, int m, int64_t ld, const float *mean,
 hipError_t launch_project(const void *Y, int dt, int64_t n, int m, int64_t ld, const float *mean,
                           const float *V, int k, float *Q, hipStream_t st)
 {
-    const bool v4 = vec4_ok(Y, dt, ld);
+    const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32) return launch_t(static_cast<const float *>(Y), n, m, ld, mean, V, k, Q, st, v4);
     return launch_t(static_cast<const uint16_t *>(Y), n, m, ld, mean, V, k, Q, st, v4);
 }
