@@ -26,7 +26,7 @@ inline pca_status check_cube(const void *Y, int dt, int64_t n, int32_t m, int64_
 inline pca_status hip_status(hipError_t e) { return e == hipSuccess ? PCA_OK : PCA_ERR_HIP; }
 
 size_t center_ws(const pca::CovPlan &p, int m) { return al(p.bytes_sum) + al((size_t)m * sizeof(double)); }
-size_t cov_ws(const pca::CovPlan &p) { return al(p.bytes_S) + al(p.bytes_sum) + al(p.bytes_shift); }
+size_t cov_ws(const pca::CovPlan &p) { return al(p.bytes_S) + al(p.bytes_sum) + al(p.bytes_shift) + al(p.bytes_part2); }
 size_t jac_ws(const pca::JacPlan &p) { return al(p.bytes_log) + al(p.bytes_lam) + al(p.bytes_vu) + al(p.bytes_info); }
 
 }  // namespace
@@ -102,12 +102,13 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
     float *partS = reinterpret_cast<float *>(w);
     double *partSum = reinterpret_cast<double *>(w + al(plan.bytes_S));
     float *partShift = reinterpret_cast<float *>(w + al(plan.bytes_S) + al(plan.bytes_sum));
+    double *part2 = reinterpret_cast<double *>(w + al(plan.bytes_S) + al(plan.bytes_sum) + al(plan.bytes_shift));
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = pca::launch_cov_partial(Y, dt, n_pixels, n_bands, ld_y, input_is_centered, mode, plan, partS,
                                            partSum, partShift, st);
     if (e != hipSuccess) return PCA_ERR_HIP;
     return hip_status(pca::launch_cov_finalize(n_pixels, n_bands, input_is_centered, plan, partS, partSum,
-                                               partShift, C, mean, st));
+                                               partShift, part2, C, mean, st));
 }
 
 pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t max_sweeps, int32_t fp64_angles,

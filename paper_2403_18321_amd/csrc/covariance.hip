@@ -261,10 +261,13 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
     }
 }
 
-__global__ __launch_bounds__(1024) void cov_finalize_kernel(
+// Pass 2a: grid (block, chunk group). Every workgroup forms the band means of
+// its block's 64 bands (all chunks, float64, fixed order: identical in every
+// workgroup), then the centred second moment of its range of chunks.
+__global__ __launch_bounds__(1024) void cov_finalize_part_kernel(
     int64_t n, int m, int centered, int64_t chunk, int64_t nchunks, int nb, int nblk, int mpad,
     const float *__restrict__ partS, const double *__restrict__ partSum, const float *__restrict__ partShift,
-    float *__restrict__ C, float *__restrict__ mean)
+    double *__restrict__ part2)
 {
     constexpr int kBatch = 32;
     __shared__ double mu[64];
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(1024) void cov_finalize_kernel(
     __shared__ float shv[kBatch][64];
     __shared__ double smv[kBatch][64];
 
-    const int e = blockIdx.x;
+    const int e = blockIdx.x, gi = blockIdx.y, G = gridDim.y;
     int bi = 0, rem = e;
     while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
     const int bj = bi + rem;
@@ -283,8 +286,6 @@ __global__ __launch_bounds__(1024) void cov_finalize_kernel(
     auto band = [&](int q) { return q < 32 ? 32 * bi + q : 32 * bj + (q - 32); };
     auto pixels = [&](int64_t w) { return (double)((w * chunk + chunk < n ? w * chunk + chunk : n) - w * chunk); };
 
-    // Band means of this block's 64 bands in float64: wave w adds a contiguous
-    // range of chunks, then the 16 wave sums are added in order.
     {
         const int b = band(lane);
         const int64_t w0 = (int64_t)r * nchunks / 16, w1 = (int64_t)(r + 1) * nchunks / 16;
@@ -303,26 +304,27 @@ __global__ __launch_bounds__(1024) void cov_finalize_kernel(
     }
     __syncthreads();
 
+    const int64_t c0 = (int64_t)gi * nchunks / G, c1 = (int64_t)(gi + 1) * nchunks / G;
     double acc = 0.0;
-    for (int64_t w0 = 0; w0 < nchunks; w0 += kBatch) {
-        const int nbatch = (int)((nchunks - w0) < kBatch ? (nchunks - w0) : kBatch);
+    for (int64_t w0 = c0; w0 < c1; w0 += kBatch) {
+        const int nbatch = (int)((c1 - w0) < kBatch ? (c1 - w0) : kBatch);
         for (int t = tid; t < kBatch * 64; t += 1024) {
             const int cc = t >> 6, q = t & 63;
             const int b = band(q);
-            float sh = 0.f;
-            double sm = 0.0;
-            if (cc < nbatch && b < mpad) {
-                const int64_t w = w0 + cc;
-                sm = partSum[w * mpad + b];
-                if (!centered) sh = partShift[w * mpad + b];
-            }
-            shv[cc][q] = sh;
-            smv[cc][q] = sm;
+            const bool ok = cc < nbatch && b < mpad;
+            const int64_t w = ok ? w0 + cc : 0;
+            const int bb = ok ? b : 0;
+            const double sm = partSum[w * mpad + bb];
+            const float sh = partShift[w * mpad + bb];
+            smv[cc][q] = ok ? sm : 0.0;
+            shv[cc][q] = (ok && !centered) ? sh : 0.f;
         }
         float sv[kBatch];
 #pragma unroll
-        for (int cc = 0; cc < kBatch; ++cc)
-            sv[cc] = cc < nbatch ? partS[((w0 + cc) * nblk + e) * 1024 + tid] : 0.f;
+        for (int cc = 0; cc < kBatch; ++cc) {
+            const int64_t w = cc < nbatch ? w0 + cc : w0;
+            sv[cc] = partS[(w * nblk + e) * 1024 + tid];
+        }
         __syncthreads();
 #pragma unroll
         for (int cc = 0; cc < kBatch; ++cc) {
@@ -335,14 +337,34 @@ __global__ __launch_bounds__(1024) void cov_finalize_kernel(
         }
         __syncthreads();
     }
+    part2[((int64_t)gi * nblk + e) * 1024 + tid] = acc;
+    if (gi == 0 && e == 0 && tid == 0) part2[(int64_t)G * nblk * 1024] = 0.0;   // unused pad
+    if (gi == 0 && bi == bj && tid < 32) part2[(int64_t)G * nblk * 1024 + 1 + 32 * bi + tid] = mu[tid];
+}
 
+// Pass 2b: the chunk groups added in order, divided by N - 1, mirrored.
+__global__ __launch_bounds__(1024) void cov_finalize_sum_kernel(int64_t n, int m, int centered, int nb, int nblk,
+                                                                int G, const double *__restrict__ part2,
+                                                                float *__restrict__ C, float *__restrict__ mean)
+{
+    const int e = blockIdx.x;
+    int bi = 0, rem = e;
+    while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
+    const int bj = bi + rem;
+    const int tid = threadIdx.x;
+    const int r = tid >> 6, lane = tid & 63;
+    const int il = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int jl = lane & 31;
+    double acc = 0.0;
+    for (int gi = 0; gi < G; ++gi) acc += part2[((int64_t)gi * nblk + e) * 1024 + tid];
     const int i = 32 * bi + il, j = 32 * bj + jl;
     if (i < m && j < m && !(bi == bj && i > j)) {
         const float val = (float)(acc / (double)(n - 1));
         C[(int64_t)i * m + j] = val;
         C[(int64_t)j * m + i] = val;
     }
-    if (mean && !centered && bi == bj && tid < 32 && 32 * bi + tid < m) mean[32 * bi + tid] = (float)mu[tid];
+    if (mean && !centered && bi == bj && tid < 32 && 32 * bi + tid < m)
+        mean[32 * bi + tid] = (float)part2[(int64_t)G * nblk * 1024 + 1 + 32 * bi + tid];
 }
 
 template <typename T, int VEC>
@@ -384,6 +406,8 @@ CovPlan cov_plan(int64_t n, int m)
     p.bytes_S = (size_t)p.nchunks * p.nblk * 1024 * sizeof(float);
     p.bytes_sum = (size_t)p.nchunks * p.mpad * sizeof(double);
     p.bytes_shift = (size_t)p.nchunks * p.mpad * sizeof(float);
+    p.groups = (int)(p.nchunks < 8 ? p.nchunks : 8);
+    p.bytes_part2 = ((size_t)p.groups * p.nblk * 1024 + 1 + 256) * sizeof(double);
     return p;
 }
 
@@ -403,10 +427,14 @@ hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t l
 }
 
 hipError_t launch_cov_finalize(int64_t n, int m, int centered, const CovPlan &plan, const float *partS,
-                               const double *partSum, const float *partShift, float *C, float *mean, hipStream_t st)
+                               const double *partSum, const float *partShift, double *part2, float *C, float *mean,
+                               hipStream_t st)
 {
-    hipLaunchKernelGGL(cov_finalize_kernel, dim3((unsigned)plan.nblk), dim3(1024), 0, st, n, m, centered, plan.chunk,
-                       plan.nchunks, plan.nb, plan.nblk, plan.mpad, partS, partSum, partShift, C, mean);
+    hipLaunchKernelGGL(cov_finalize_part_kernel, dim3((unsigned)plan.nblk, (unsigned)plan.groups), dim3(1024), 0, st,
+                       n, m, centered, plan.chunk, plan.nchunks, plan.nb, plan.nblk, plan.mpad, partS, partSum,
+                       partShift, part2);
+    hipLaunchKernelGGL(cov_finalize_sum_kernel, dim3((unsigned)plan.nblk), dim3(1024), 0, st, n, m, centered,
+                       plan.nb, plan.nblk, plan.groups, (const double *)part2, C, mean);
     return hipGetLastError();
 }
 

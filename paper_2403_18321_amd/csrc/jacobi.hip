@@ -11,18 +11,25 @@
 // B_k, so pair k is always (T_k, B_k). The matrix is kept in slot
 // coordinates and physically permuted after every step, so that the pairs
 // never move: the permutation is the same fixed map every step and each
-// thread's source and destination LDS addresses are computed once. Storage
-// (LDS, float32): T-T and B-B off-diagonal entries as packed strict upper
-// triangles, T-B entries as a full (n/2) x (n/2 + 1) array (T_k-B_k are the
-// pivots); the diagonal is float64 in a separate double-buffered array.
-// After n - 1 steps the slots are back in their initial places.
+// thread's source and destination LDS addresses are computed once. After
+// n - 1 steps the slots are back in their initial places.
 //
-// jacobi_kernel (one workgroup, one CU). A step:
-//   a. every thread rotates its 2x2 blocks (pairs k < l): rows by R_k^T,
-//      columns by R_l -- the row and column updates of C_k = P^T C P,
-//      equation (8), for all pairs of the step at once;
+// Storage (LDS). The off-diagonal entries form 2x2 blocks (k, l), k < l:
+// rows (T_k, B_k) x columns (T_l, B_l), 16 bytes each, read with one b128
+// load; block row k is contiguous and starts at a padded offset (3k mod 16
+// blocks) so that the lanes of a wave, which hold the same place in
+// consecutive rows, read distinct banks; the four components sit in a
+// per-row swizzled order so that their b32 stores hit distinct banks too.
+// The pivots (T_k, B_k) are not stored: the thread that produces one
+// computes its rotation on the spot. The diagonal is float64 in a separate
+// double-buffered array, as are the rotations (tan, cos).
+//
+// jacobi_kernel (one workgroup of 512 threads, one CU). A step:
+//   a. every thread rotates its 2x2 blocks: rows by R_k^T, columns by R_l --
+//      the row and column updates of C_k = P^T C P, equation (8), for all
+//      pairs of the step at once;
 //   b. barrier; the rotated entries are written to their permuted places.
-//      Whoever writes a pivot of the next step also computes that pivot's
+//      Whoever produces a pivot of the next step also computes that pivot's
 //      rotation (equations (2)-(5) with (7), as t = sgn(theta) / (|theta| +
 //      sqrt(1 + theta^2)), float64 by default), the new diagonal entries
 //      a_pp - t a_pq and a_qq + t a_pq, and logs (cos, sin).
@@ -48,24 +55,22 @@ namespace {
 
 constexpr int kJThreads = 512;
 constexpr int kMaxP = 128;
-constexpr int kMaxSlotFloats = 128 * 127 + 128 * 129;
-constexpr int kLoadPerThread = 64;                       // loads in flight per pass
-constexpr double kFloorRel2 = 3.552713678800501e-15;     // (2^-24)^2
+constexpr int kMaxRowBlocks = 9088;   // padded block rows for 128 pairs (see row_start)
+constexpr int kBlockPad = 32;         // tail that segment reads may run into
+constexpr int kCsPad = 32;
+constexpr int kLoadPerThread = 64;    // loads in flight per pass
+constexpr double kFloorRel2 = 3.552713678800501e-15;   // (2^-24)^2
 
 struct Slots {
-    int P, n, PT, baseBB, baseTB;
+    int P, n;
+    const int *R;   // first block of each block row (LDS)
 
-    __device__ void init(int n_) {
+    __device__ void init(int n_, const int *R_, const unsigned char *W_) {
         n = n_;
         P = n_ / 2;
-        PT = P + 1;
-        baseBB = P * (P - 1) / 2;
-        baseTB = P * (P - 1);
+        R = R_;
+        W = W_;
     }
-    __device__ int total() const { return baseTB + P * PT; }
-    __device__ int tt(int a, int b) const { return a * (2 * P - a - 1) / 2 + (b - a - 1); }   // a < b
-    __device__ int bb(int a, int b) const { return baseBB + tt(a, b); }
-    __device__ int tb(int t, int b) const { return baseTB + t * PT + b; }
     // Slot ids: T_k = k, B_k = P + k. Where a slot's entries go after a step:
     // the index at position j moves to position j - 1 (j >= 2), position 1
     // wraps to n - 1, position 0 stays. (Turning the circle this way round
@@ -81,33 +86,80 @@ struct Slots {
         const int k = x - P;
         return k <= P - 2 ? P + k + 1 : P - 1;
     }
-    // LDS index of the off-diagonal entry (x, y), x != y.
-    __device__ int addr(int x, int y) const {
-        const bool xt = x < P, yt = y < P;
-        if (xt && yt) return x < y ? tt(x, y) : tt(y, x);
-        if (!xt && !yt) {
-            const int a = x - P, b = y - P;
-            return a < b ? bb(a, b) : bb(b, a);
+    // Index of block (k, l), k < l: block row k is stored contiguously from
+    // R[k]; rows start at R[k] = 3k (mod 16) so that the lanes of a wave,
+    // which take the same place in consecutive rows, hit distinct LDS banks.
+    __device__ int bi(int k, int l) const { return R[k] + (l - k - 1); }
+    // Component c = 2 [row is a B slot] + [column is a B slot] of a block in
+    // block row a is stored at position c ^ W[a] of the block's 16 bytes
+    // (T/B rows and/or columns swapped). Lanes of a half-wave take rows
+    // k .. k+31 and write a component of a block in row k -/+ 1 whose index
+    // repeats mod 8 every 8 rows; the b32 write path resolves 32 banks per 32
+    // lanes, so the position must differ between rows 8 apart. W[a] is the
+    // running XOR of (j >> 3) & 3 over j = 1 .. a: a row's source swizzle and
+    // its neighbour's destination swizzle then differ by (a >> 3) & 3.
+    const unsigned char *W;
+    __device__ int sw(int a) const { return W[a]; }
+    // Where the off-diagonal entry (x, y), x != y, lives: a float index into
+    // the block rows, or -1 - k for the pivot (T_k, B_k).
+    __device__ int code(int x, int y) const {
+        int a = x, b = y, xb = 0, yb = 0;
+        if (a >= P) { a -= P; xb = 1; }
+        if (b >= P) { b -= P; yb = 1; }
+        if (a == b) return -1 - a;
+        if (a > b) {
+            const int t = a; a = b; b = t;
+            const int u = xb; xb = yb; yb = u;
         }
-        return xt ? tb(x, y - P) : tb(y, x - P);
-    }
-    // Pair whose pivot (T_k, B_k) the entry (x, y) is, or -1.
-    __device__ int pivot_of(int x, int y) const {
-        if (x < P && y == x + P) return x;
-        if (y < P && x == y + P) return y;
-        return -1;
+        return 4 * bi(a, b) + ((2 * xb + yb) ^ W[a]);
     }
     // Slot of physical index i at the start of a sweep, and back.
     __device__ int slot_of(int i) const { return i < P ? i : P + (n - 1 - i); }
     __device__ int phys(int x) const { return x < P ? x : n - 1 - (x - P); }
 };
 
+// Start of each padded block row (R[0 .. P]).
+__host__ __device__ inline int row_start_next(int P, int k, int Rk)
+{
+    const int e = Rk + (P - 1 - k);
+    return e + (((3 * (k + 1) - e) % 16) + 16) % 16;
+}
+
+// Generic blocks of row k: l = k + 3 .. P - 2. For them every rotated entry
+// lands in a regular component of another block at a fixed offset, so a run
+// of them along a row moves by constant strides.
+__host__ __device__ inline int generic_len(int P, int k) { return (P >= 5 && k <= P - 5) ? P - k - 4 : 0; }
+// Generic segments with segment index s (one per row that is long enough).
+__host__ __device__ inline int segments_at(int P, int L, int s)
+{
+    const int c = P - 4 - L * s;
+    return c > 0 ? c : 0;
+}
+
+// 1/sqrt(x) and 1/x in float64 from the hardware estimates refined by two
+// Newton steps each (the estimates carry roughly single precision, so two
+// steps reach double precision).
+__device__ inline double rsqrt64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+}
+__device__ inline double rcp64(double x)
+{
+    double q = __builtin_amdgcn_rcp(x);
+    q = q * fma(-x, q, 2.0);
+    q = q * fma(-x, q, 2.0);
+    return q;
+}
+
 // Rotation of a pivot pair, equations (2)-(5) with (7):
 //   theta = (a_qq - a_pp) / (2 a_pq), t = sgn(theta) / (|theta| + sqrt(1 + theta^2))
 // evaluated as t = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
-// (the same number), cos = 1/sqrt(1 + t^2), sin = t cos. Skipped (cos = 1,
-// sin = 0) when |a_pq| is at the float32 rounding floor.
-__device__ inline void rotation(double app, double aqq, float apq, double floor_abs, int fp64, float2 &cs,
+// (the same number), cos = 1/sqrt(1 + t^2), sin = t cos. Skipped (t = 0,
+// cos = 1) when |a_pq| is at the float32 rounding floor. Returns (t, cos).
+__device__ inline void rotation(double app, double aqq, float apq, double floor_abs, int fp64, float2 &tc,
                                 double &dT, double &dB, float &pv)
 {
     const double a = (double)apq;
@@ -116,23 +168,22 @@ __device__ inline void rotation(double app, double aqq, float apq, double floor_
         double t;
         if (fp64) {
             const double d = aqq - app;
-            const double r = sqrt(d * d + 4.0 * a * a);
-            t = (d >= 0.0 ? 2.0 * a : -2.0 * a) / (fabs(d) + r);
-            const double c = rsqrt(1.0 + t * t);
-            cs = make_float2((float)c, (float)(t * c));
+            const double x = fma(d, d, 4.0 * a * a);
+            const double r = x * rsqrt64(x);
+            t = (d >= 0.0 ? 2.0 * a : -2.0 * a) * rcp64(fabs(d) + r);
+            tc = make_float2((float)t, (float)rsqrt64(fma(t, t, 1.0)));
         } else {
             const float df = (float)aqq - (float)app;
             const float rf = sqrtf(df * df + 4.f * apq * apq);
             const float tf = (df >= 0.f ? 2.f * apq : -2.f * apq) / (fabsf(df) + rf);
-            const float c = 1.f / sqrtf(1.f + tf * tf);
-            cs = make_float2(c, tf * c);
+            tc = make_float2(tf, 1.f / sqrtf(1.f + tf * tf));
             t = tf;
         }
         dT = app - t * a;
         dB = aqq + t * a;
         pv = 0.f;
     } else {
-        cs = make_float2(1.f, 0.f);
+        tc = make_float2(0.f, 1.f);
         dT = app;
         dB = aqq;
         pv = apq;
@@ -163,33 +214,139 @@ __device__ inline int block_sum_i(int v, int *red)
     return t;
 }
 
-template <int MAXB>
+// Work of one thread in a step (fixed for the whole run):
+//   a generic segment: blocks (k, l0 .. l0 + len - 1) of one row, len <= L.
+//     Source and destination addresses are the segment's base plus a
+//     constant per block, so the step code holds five base registers and
+//     uses immediate LDS offsets (one b128 read per block). Segments are
+//     numbered segment-index-major, so the lanes of a wave take the same
+//     segment of consecutive rows;
+//   one special block (the diagonals next to the pivots and the last column),
+//     with explicit destination codes; a special block that produces a pivot
+//     of the next step also computes that pivot's rotation;
+//   thread j < P moves pair j's rotated pivot to its next place and logs the
+//     rotation.
+template <int L>
 __global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restrict__ C, int m, int n, double tol,
                                                            int max_sweeps, int fp64_angles,
                                                            double *__restrict__ lam_u, float2 *__restrict__ rlog,
                                                            pca_info *__restrict__ info)
 {
-    __shared__ float A[kMaxSlotFloats];
+    __shared__ float4 blk[kMaxRowBlocks + kBlockPad];
     __shared__ double dg[2][256];
-    __shared__ float2 csb[2][kMaxP];
-    __shared__ float pvb[2][kMaxP];
+    __shared__ float2 csb[2][kMaxP + kCsPad];   // (tan, cos) of each pair's rotation
+    __shared__ float pvb[2][kMaxP];             // pivot after its rotation (0 unless skipped)
+    __shared__ float pva[kMaxP];                // pivot before its rotation
+    __shared__ int rowR[kMaxP + 1];
+    __shared__ unsigned char rowW[kMaxP];
     __shared__ double redd[16];
     __shared__ int redi[16];
     __shared__ int bad;
 
-    Slots S;
-    S.init(n);
-    const int P = S.P;
     const int tid = threadIdx.x;
-    const int total = S.total();
-
-    if (tid == 0) bad = 0;
-    for (int e = tid; e < total; e += kJThreads) A[e] = 0.f;
-    for (int i = tid; i < 256; i += kJThreads) { dg[0][i] = 0.0; dg[1][i] = 0.0; }
+    const int P = n / 2;
+    if (tid == 0) {
+        int r = 0;
+        rowR[0] = 0;
+        int w = 0;
+        for (int k = 0; k < P; ++k) {
+            r = row_start_next(P, k, r);
+            rowR[k + 1] = r;
+            w ^= (k >> 3) & 3;
+            rowW[k] = (unsigned char)w;
+        }
+        bad = 0;
+    }
     __syncthreads();
+    Slots S;
+    S.init(n, rowR, rowW);
+    const int nbf = 4 * rowR[P];   // floats of the padded block rows
+    float *Af = reinterpret_cast<float *>(blk);
 
-    // Load the upper triangle of C into slot coordinates (each pass issues all
-    // its global loads before any LDS store).
+    // Generic segment of this thread.
+    int gk = 0, l0 = 0, len = 0;
+    {
+        int cum = 0, sg = 0;
+        while (true) {
+            const int c = segments_at(P, L, sg);
+            if (c == 0 || tid < cum + c) {
+                if (c > 0) {
+                    gk = tid - cum;
+                    l0 = gk + 3 + L * sg;
+                    len = min(L, P - 1 - l0);
+                }
+                break;
+            }
+            cum += c;
+            ++sg;
+        }
+    }
+    // Register r of a block read from row k holds component r ^ sw(k); the
+    // rotation is applied in that order with the tangents of swapped pairs
+    // negated (swapping T and B of a pair turns its rotation into the one by
+    // the opposite angle), and result r goes to component r ^ sw(k)'s place.
+    int gsrc = 0, gd[4] = {0, 0, 0, 0};
+    float gsr = 1.f, gsc = 1.f;
+    if (len > 0) {
+        gsrc = S.bi(gk, l0);
+        const int w = S.sw(gk);
+        gsr = (w & 2) ? -1.f : 1.f;
+        gsc = (w & 1) ? -1.f : 1.f;
+        const int xs[2] = {gk, P + gk}, ys[2] = {l0, P + l0};
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) gd[(2 * a + b) ^ w] = S.code(S.next(xs[a]), S.next(ys[b]));
+    }
+
+    // Special block of this thread: the pivot sources (k, k + 2), (0, 1) and
+    // (P-2, P-1) first, then the other (k, k + 1), then (k, P - 1).
+    int ssrc = 0, sk = 0, sl = 0, sd[4] = {0, 0, 0, 0};
+    int mine0 = -1, mc0 = 0, mine1 = -1, mc1 = 0;
+    float ssr = 1.f, ssc = 1.f;
+    bool has_sp = false;
+    {
+        const int nd2 = P >= 2 ? P - 2 : 0;
+        int k = -1, l = -1;
+        const int i = tid;
+        if (P >= 2) {
+            if (i < nd2) { k = i; l = i + 2; }
+            else if (i == nd2) { k = 0; l = 1; }
+            else if (P >= 3 && i == nd2 + 1) { k = P - 2; l = P - 1; }
+            else if (P >= 4) {
+                int j = i - nd2 - 2;
+                if (j < P - 3) { k = 1 + j; l = 2 + j; }
+                else if ((j -= P - 3) < P - 3) { k = j; l = P - 1; }
+            }
+        }
+        if (k >= 0) {
+            has_sp = true;
+            ssrc = S.bi(k, l);
+            sk = k;
+            sl = l;
+            const int w = S.sw(k);
+            ssr = (w & 2) ? -1.f : 1.f;
+            ssc = (w & 1) ? -1.f : 1.f;
+            const int xs[2] = {k, P + k}, ys[2] = {l, P + l};
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const int c = S.code(S.next(xs[a]), S.next(ys[b]));
+                    const int r = (2 * a + b) ^ w;
+                    sd[r] = c;
+                    if (c < 0) {
+                        if (mine0 < 0) { mine0 = -1 - c; mc0 = r; }
+                        else { mine1 = -1 - c; mc1 = r; }
+                    }
+                }
+        }
+    }
+    // Where thread j's rotated pivot goes.
+    const int pcode = tid < P ? S.code(S.next(tid), S.next(P + tid)) : 0;
+
+    // ---- load C (upper triangle) into the slot layout ---------------------
+    for (int e = tid; e < 4 * (kMaxRowBlocks + kBlockPad); e += kJThreads) Af[e] = 0.f;
+    for (int i = tid; i < 256; i += kJThreads) { dg[0][i] = 0.0; dg[1][i] = 0.0; }
+    for (int i = tid; i < kMaxP; i += kJThreads) { pva[i] = 0.f; pvb[0][i] = 0.f; pvb[1][i] = 0.f; }
+    for (int i = tid; i < 2 * (kMaxP + kCsPad); i += kJThreads) (&csb[0][0])[i] = make_float2(0.f, 1.f);
+    __syncthreads();
     {
         const int mm = m * m;
         int nonfin = 0;
@@ -208,8 +365,13 @@ __global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restri
                     if (j >= i) {
                         if (!isfinite(tmp[q])) nonfin = 1;
                         const int si = S.slot_of(i), sj = S.slot_of(j);
-                        if (i == j) dg[0][si] = (double)tmp[q];
-                        else A[S.addr(si, sj)] = tmp[q];
+                        if (i == j) {
+                            dg[0][si] = (double)tmp[q];
+                        } else {
+                            const int c = S.code(si, sj);
+                            if (c >= 0) Af[c] = tmp[q];
+                            else pva[-1 - c] = tmp[q];
+                        }
                     }
                 }
             }
@@ -218,85 +380,38 @@ __global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restri
     }
     __syncthreads();
 
+    auto offnorm2 = [&]() -> double {
+        double part = 0.0;
+        for (int e = tid; e < nbf; e += kJThreads) part += (double)Af[e] * (double)Af[e];
+        for (int j = tid; j < P; j += kJThreads) part += (double)pva[j] * (double)pva[j];
+        return 2.0 * block_sum_d(part, redd);
+    };
+
     double fro2;
     {
         double part = 0.0;
-        for (int e = tid; e < total; e += kJThreads) part += 2.0 * (double)A[e] * (double)A[e];
         for (int i = tid; i < n; i += kJThreads) part += dg[0][i] * dg[0][i];
-        fro2 = block_sum_d(part, redd);
+        fro2 = block_sum_d(part, redd) + offnorm2();
     }
-    const bool nonfinite = bad != 0;
+    const bool failed = bad != 0;
     const double floor_abs = 5.9604644775390625e-08 * sqrt(fro2) / (double)m;
 
-    // This thread's blocks (k, l), k < l, of the pair grid: source and
-    // destination LDS indices of the entries (T_k,T_l), (T_k,B_l), (B_k,T_l),
-    // (B_k,B_l), and which of them become pivots of the next step.
-    const int nblocks = P * (P - 1) / 2;
-    int bk[MAXB], bl[MAXB], be[MAXB], sTB[MAXB], sBT[MAXB], dst[MAXB][4];
-    // Pairs whose next pivot this thread writes (at most two for any n <= 256
-    // with 512 threads; a third would be reported as a failure).
-    int piv0 = -1, piv1 = -1, piv_over = 0;
-    int myn = 0;
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-        int e = tid + q * kJThreads;
-        bk[q] = bl[q] = be[q] = sTB[q] = sBT[q] = 0;
-        dst[q][0] = dst[q][1] = dst[q][2] = dst[q][3] = 0;
-        if (e < nblocks) {
-            be[q] = e;
-            int k = 0;
-            while (e >= P - 1 - k) { e -= P - 1 - k; ++k; }
-            const int l = k + 1 + e;
-            bk[q] = k;
-            bl[q] = l;
-            sTB[q] = S.tb(k, l);
-            sBT[q] = S.tb(l, k);
-            const int xs[2] = {k, P + k}, ys[2] = {l, P + l};
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int nx = S.next(xs[a]), ny = S.next(ys[b]);
-                    dst[q][2 * a + b] = S.addr(nx, ny);
-                    const int kp = S.pivot_of(nx, ny);
-                    if (kp >= 0) {
-                        if (piv0 < 0) piv0 = kp;
-                        else if (piv1 < 0) piv1 = kp;
-                        else piv_over = 1;
-                    }
-                }
-            }
-            myn = q + 1;
-        }
-    }
-    // Thread k < P moves pivot k after each step.
-    int pdst = 0, pdst_pivot = -1;
-    if (tid < P) {
-        const int nx = S.next(tid), ny = S.next(P + tid);
-        pdst = S.addr(nx, ny);
-        pdst_pivot = S.pivot_of(nx, ny);
-    }
-
-    if (piv_over) atomicOr(&bad, 2);
-    __syncthreads();
-    const bool failed = nonfinite || bad != 0;
-
     // Rotation of pair k for the step whose diagonal is in dg[src]; writes
-    // its (cos, sin) and moved pivot into slot `par`, the rotated diagonal
+    // (tan, cos) and the rotated pivot into slot `par`, the rotated diagonal
     // (already permuted) into dg[dsto].
     auto rotate = [&](int k, float apq, int src, int dsto, int par) {
-        float2 cs;
+        float2 tc;
         double dT, dB;
         float pv;
-        rotation(dg[src][k], dg[src][P + k], apq, floor_abs, fp64_angles, cs, dT, dB, pv);
-        csb[par][k] = cs;
+        rotation(dg[src][k], dg[src][P + k], apq, floor_abs, fp64_angles, tc, dT, dB, pv);
+        csb[par][k] = tc;
         pvb[par][k] = pv;
         dg[dsto][S.next(k)] = dT;
         dg[dsto][S.next(P + k)] = dB;
     };
 
     // Rotations of step 0.
-    if (tid < P && !failed) rotate(tid, A[S.tb(tid, tid)], 0, 1, 0);
+    if (tid < P && !failed) rotate(tid, pva[tid], 0, 1, 0);
     __syncthreads();
 
     int sweeps = 0, converged = 0, floor_hit = 0;
@@ -305,52 +420,83 @@ __global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restri
     double off2 = 0.0;
     int64_t g = 0;
 
+    // Rows T_k, B_k by R_k^T, then columns T_l, B_l by R_l, in the tangent
+    // form c (x - t y), the two cosines applied at the end.
+    auto rot2 = [](float4 x, float tk, float ckc, float tl, float clc) -> float4 {
+        const float u0 = fmaf(-tk, x.z, x.x), u1 = fmaf(-tk, x.w, x.y);
+        const float u2 = fmaf(tk, x.x, x.z), u3 = fmaf(tk, x.y, x.w);
+        const float cc = ckc * clc;
+        return make_float4(cc * fmaf(-tl, u1, u0), cc * fmaf(tl, u0, u1), cc * fmaf(-tl, u3, u2),
+                           cc * fmaf(tl, u2, u3));
+    };
+    auto pick = [](float4 z, int c) -> float { return c == 0 ? z.x : (c == 1 ? z.y : (c == 2 ? z.z : z.w)); };
+
     while (!failed) {
-        {
-            double part = 0.0;
-            for (int e = tid; e < total; e += kJThreads) part += (double)A[e] * (double)A[e];
-            off2 = 2.0 * block_sum_d(part, redd);
-        }
+        off2 = offnorm2();
         if (off2 <= lim2) { converged = 1; break; }
         if (sweeps >= max_sweeps) break;
 
         int cnt = 0;
         for (int sIn = 0; sIn < n - 1; ++sIn, ++g) {
             const int par = (int)(g & 1);
-            float z[MAXB][4];
+            const float2 *cs = csb[par];
+            float4 z[L];
+            if (len > 0) {
+                const float2 ck = cs[gk];
+                const float tk = gsr * ck.x;
+                const float4 *src = &blk[gsrc];
+                const float2 *csl = &cs[l0];
 #pragma unroll
-            for (int q = 0; q < MAXB; ++q) {
-                if (q < myn) {
-                    const float2 ck = csb[par][bk[q]], cl = csb[par][bl[q]];
-                    const int e = be[q];
-                    const float x0 = A[e], x1 = A[sTB[q]], x2 = A[sBT[q]], x3 = A[S.baseBB + e];
-                    // Rows T_k, B_k by R_k^T, then columns T_l, B_l by R_l.
-                    const float y0 = ck.x * x0 - ck.y * x2, y1 = ck.x * x1 - ck.y * x3;
-                    const float y2 = ck.y * x0 + ck.x * x2, y3 = ck.y * x1 + ck.x * x3;
-                    z[q][0] = y0 * cl.x - y1 * cl.y;
-                    z[q][1] = y0 * cl.y + y1 * cl.x;
-                    z[q][2] = y2 * cl.x - y3 * cl.y;
-                    z[q][3] = y2 * cl.y + y3 * cl.x;
+                for (int q = 0; q < L; ++q) {
+                    const float2 cl = csl[q];
+                    z[q] = rot2(src[q], tk, ck.y, gsc * cl.x, cl.y);
                 }
+            }
+            float4 zs = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (has_sp) {
+                const float2 ck = cs[sk], cl = cs[sl];
+                zs = rot2(blk[ssrc], ssr * ck.x, ck.y, ssc * cl.x, cl.y);
             }
             __syncthreads();
+            if (len > 0) {
 #pragma unroll
-            for (int q = 0; q < MAXB; ++q) {
-                if (q < myn) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) A[dst[q][c]] = z[q][c];
+                for (int q = 0; q < L; ++q) {
+                    if (q < len) {
+                        Af[gd[0] + 4 * q] = z[q].x;
+                        Af[gd[1] + 4 * q] = z[q].y;
+                        Af[gd[2] + 4 * q] = z[q].z;
+                        Af[gd[3] + 4 * q] = z[q].w;
+                    }
                 }
             }
-            // Next step's rotations of the pivots this thread just wrote.
-            if (piv0 >= 0) rotate(piv0, A[S.tb(piv0, piv0)], par ^ 1, par, par ^ 1);
-            if (piv1 >= 0) rotate(piv1, A[S.tb(piv1, piv1)], par ^ 1, par, par ^ 1);
+            if (has_sp) {
+                if (sd[0] >= 0) Af[sd[0]] = zs.x;
+                if (sd[1] >= 0) Af[sd[1]] = zs.y;
+                if (sd[2] >= 0) Af[sd[2]] = zs.z;
+                if (sd[3] >= 0) Af[sd[3]] = zs.w;
+                // The next step's rotation of the pivot this block produced.
+                if (mine0 >= 0) {
+                    const float pv = pick(zs, mc0);
+                    pva[mine0] = pv;
+                    rotate(mine0, pv, par ^ 1, par, par ^ 1);
+                }
+                if (mine1 >= 0) {
+                    const float pv = pick(zs, mc1);
+                    pva[mine1] = pv;
+                    rotate(mine1, pv, par ^ 1, par, par ^ 1);
+                }
+            }
             if (tid < P) {
-                const float2 c = csb[par][tid];
-                cnt += c.y != 0.f;
-                rlog[g * P + tid] = c;
+                const float2 tc = cs[tid];
+                cnt += tc.x != 0.f;
+                rlog[g * P + tid] = make_float2(tc.y, tc.x * tc.y);
                 const float pv = pvb[par][tid];
-                A[pdst] = pv;
-                if (pdst_pivot >= 0) rotate(pdst_pivot, pv, par ^ 1, par, par ^ 1);
+                if (pcode >= 0) {
+                    Af[pcode] = pv;
+                } else {
+                    pva[-1 - pcode] = pv;
+                    rotate(-1 - pcode, pv, par ^ 1, par, par ^ 1);
+                }
             }
             __syncthreads();
         }
@@ -360,11 +506,7 @@ __global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restri
         if (applied == 0) { converged = 1; floor_hit = 1; break; }
     }
 
-    if (!converged || floor_hit || failed) {
-        double part = 0.0;
-        for (int e = tid; e < total; e += kJThreads) part += (double)A[e] * (double)A[e];
-        off2 = 2.0 * block_sum_d(part, redd);
-    }
+    if (!converged || floor_hit || failed) off2 = offnorm2();
     const int fin = (int)(g & 1);
     for (int x = tid; x < n; x += kJThreads) lam_u[S.phys(x)] = failed ? (double)NAN : dg[fin][x];
     if (tid == 0) {
@@ -394,7 +536,7 @@ __global__ __launch_bounds__(kReplayThreads) void vreplay_kernel(int n, int rows
     __shared__ float vb[2][kReplayMaxRows][256];
     __shared__ float2 lcs[2][kReplayBatch][kMaxP];
     Slots S;
-    S.init(n);
+    S.init(n, nullptr, nullptr);
     const int P = S.P;
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * rows;
@@ -513,12 +655,20 @@ __global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const doub
     if (blockIdx.x == 0 && tid == 0 && info_out) *info_out = *info_ws;
 }
 
-template <int MAXB>
+template <int L>
 void launch_jac(const float *C, int m, int n, double tol, int max_sweeps, int fp64_angles, double *lam_u,
                 float2 *rlog, pca_info *info_ws, hipStream_t st)
 {
-    hipLaunchKernelGGL(jacobi_kernel<MAXB>, dim3(1), dim3(kJThreads), 0, st, C, m, n, tol, max_sweeps, fp64_angles,
+    hipLaunchKernelGGL(jacobi_kernel<L>, dim3(1), dim3(kJThreads), 0, st, C, m, n, tol, max_sweeps, fp64_angles,
                        lam_u, rlog, info_ws);
+}
+
+// Generic segments of length at most L for P pairs.
+int jac_segments(int P, int L)
+{
+    int s = 0;
+    for (int k = 0; k < P; ++k) s += (generic_len(P, k) + L - 1) / L;
+    return s;
 }
 
 }  // namespace
@@ -542,14 +692,22 @@ hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int 
 {
     const int n = plan.me;
     const int P = plan.npairs;
-    const int nblocks = P * (P - 1) / 2;
-    const int need = (nblocks + kJThreads - 1) / kJThreads;
-    if (need <= 1) launch_jac<1>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st);
-    else if (need <= 2) launch_jac<2>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st);
-    else if (need <= 4) launch_jac<4>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st);
-    else if (need <= 8) launch_jac<8>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st);
-    else if (need <= 13) launch_jac<13>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st);
-    else launch_jac<16>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st);
+    // Shortest segment length (odd, so that the lanes of a wave hit distinct
+    // LDS banks) that gives every segment its own thread.
+    int L = 1;
+    while (L < 19 && jac_segments(P, L) > kJThreads) L += 2;
+    switch (L) {
+    case 1: launch_jac<1>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 3: launch_jac<3>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 5: launch_jac<5>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 7: launch_jac<7>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 9: launch_jac<9>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 11: launch_jac<11>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 13: launch_jac<13>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 15: launch_jac<15>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 17: launch_jac<17>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    default: launch_jac<19>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    }
     int rows = kReplayThreads / P;
     if (rows > kReplayMaxRows) rows = kReplayMaxRows;
     const unsigned nwg = (unsigned)((n + rows - 1) / rows);

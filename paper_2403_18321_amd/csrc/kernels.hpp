@@ -25,6 +25,8 @@ struct CovPlan {
     size_t bytes_S;    // partial second moments, float32
     size_t bytes_sum;  // partial sums, float64
     size_t bytes_shift;  // per-chunk shifts, float32
+    int groups;          // chunk groups of the first finalize pass
+    size_t bytes_part2;  // float64 partial results of those groups + means
 };
 CovPlan cov_plan(int64_t n, int m);
 
@@ -32,8 +34,8 @@ hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t l
                               int mode, const CovPlan &plan, float *partS, double *partSum,
                               float *partShift, hipStream_t st);
 hipError_t launch_cov_finalize(int64_t n, int m, int centered, const CovPlan &plan, const float *partS,
-                               const double *partSum, const float *partShift, float *C, float *mean,
-                               hipStream_t st);
+                               const double *partSum, const float *partShift, double *part2, float *C,
+                               float *mean, hipStream_t st);
 
 // ---- centring --------------------------------------------------------------
 hipError_t launch_center(const void *Y, int dt, int64_t n, int m, int64_t ld, float *mean,
