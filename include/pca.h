@@ -89,7 +89,8 @@ const char *pca_status_string(pca_status s);
 
 /*
  * Bytes of workspace that `op` needs for the given sizes (mode: a
- * pca_cov_mode for PCA_OP_COVARIANCE; max_sweeps: for PCA_OP_JACOBI).
+ * pca_cov_mode for PCA_OP_COVARIANCE; max_sweeps: for PCA_OP_JACOBI; k: for
+ * PCA_OP_BACKWARD).
  */
 pca_status pca_workspace_size(int op, int64_t n_pixels, int32_t n_bands, int32_t k,
                               int32_t mode, int32_t max_sweeps, size_t *bytes);
@@ -158,6 +159,36 @@ pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t 
  */
 pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y,
                        const float *mean, const float *V, int32_t k, float *Q, void *stream);
+
+/*
+ * Reverse-mode derivative of the whole pipeline (band-mean removal,
+ * covariance, eigenpairs, projection; Algorithm 1, lines 2-6) for a scalar
+ * loss L. Given the loss's gradients at the forward outputs, writes dL/dY:
+ *   Xbar  = dQ V_k^T + 2 X Cbar / (N - 1),      X = Y - 1 mean^T,
+ *   Cbar  = sym(V (diag(dEig) + F o (V^T Vbar)) V^T),
+ *           Vbar = [X^T dQ + dVk | 0],  F_ij = 1/(lambda_j - lambda_i), i != j
+ *           (0 on the diagonal and where two eigenvalues are equal),
+ *   dY    = Xbar - (1/N) 1 (1^T Xbar).
+ * The eigenpair term is the first-order perturbation of a symmetric
+ * eigendecomposition; it assumes the eigenvalues that meet a nonzero F entry
+ * (those among the first k and their partners) are distinct. The sign fix and
+ * the sort of the forward pass are piecewise constant and add no term.
+ *   Y        [n_pixels][ld_y] float32 cube, the forward input.
+ *   mean     [n_bands] float32 band means written by the forward pass.
+ *   eigvals  [n_bands] float32, V [n_bands][n_bands] float32 (column i =
+ *            eigenvector i): the forward's eigenpairs.
+ *   k        kept components, 1 <= k <= n_bands.
+ *   dQ       [n_pixels][k] dL/dQ, or NULL (zero).
+ *   dEig     [n_bands] dL/d eigvals, or NULL (zero).
+ *   dVk      [n_bands][k] dL/dV[:, :k], or NULL (zero).
+ *   dY       [n_pixels][ld_dy] float32 out, ld_dy >= n_bands.
+ *   ws       workspace of pca_workspace_size(PCA_OP_BACKWARD, n_pixels, n_bands, k, ...).
+ * Float64 is used for every reduction over pixels and for the small
+ * bands x bands algebra; the final pixel pass is a float32 MFMA product.
+ */
+pca_status pca_backward(const float *Y, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,
+                        const float *eigvals, const float *V, int32_t k, const float *dQ, const float *dEig,
+                        const float *dVk, float *dY, int64_t ld_dy, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -15,10 +15,12 @@ from ._lib import (  # noqa: F401
     PCA_OP_CENTER,
     PCA_OP_COVARIANCE,
     PCA_OP_JACOBI,
+    PCA_OP_BACKWARD,
     PCA_OP_PROJECT,
     PCAError,
     library,
     new_info,
+    pca_backward,
     pca_center,
     pca_covariance,
     pca_jacobi_eigh,
@@ -27,4 +29,4 @@ from ._lib import (  # noqa: F401
     read_info,
     workspace,
 )
-from .api import DEFAULT_MAX_SWEEPS, DEFAULT_TOL, PCAPipeline, PCAResult, run  # noqa: F401
+from .api import DEFAULT_MAX_SWEEPS, DEFAULT_TOL, PCAFunction, PCAPipeline, PCAResult, pca_autograd, run  # noqa: F401

@@ -31,7 +31,7 @@ INFO_BYTES = struct.calcsize(INFO_FORMAT)
 INFO_FIELDS = ("sweeps", "converged", "nonfinite", "floor_hit", "off_rel", "rotations", "steps", "n_bands")
 
 EXPORTS = ("pca_status_string", "pca_workspace_size", "pca_center", "pca_covariance",
-           "pca_jacobi_eigh", "pca_project")
+           "pca_jacobi_eigh", "pca_project", "pca_backward")
 
 
 class PCAError(RuntimeError):
@@ -66,6 +66,9 @@ def _lib() -> ctypes.CDLL:
         lib.pca_jacobi_eigh.argtypes = [_vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
         lib.pca_project.restype = ctypes.c_int
         lib.pca_project.argtypes = [_vp, ctypes.c_int, _i64, _i32, _i64, _vp, _vp, _i32, _vp, _vp]
+        lib.pca_backward.restype = ctypes.c_int
+        lib.pca_backward.argtypes = [_vp, _i64, _i32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _sz,
+                                     _vp]
         _LIB = lib
     return _LIB
 
@@ -146,6 +149,31 @@ def pca_project(Y, mean, V, k: int, Q):
     dt, n, m, ld = _cube(Y)
     _check("pca_project", _lib().pca_project(_ptr(Y), dt, n, m, ld, _ptr(mean), _ptr(V), int(k), _ptr(Q),
                                              _stream()))
+
+
+def _f32(name, t, shape):
+    """A float32 device tensor of the given shape, contiguous (rows may be
+    padded only where the C ABI takes a leading dimension)."""
+    if t is None:
+        return
+    if t.dtype != torch.float32 or not t.is_cuda or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {tuple(shape)}")
+
+
+def pca_backward(Y, mean, eigvals, V, k: int, dY, dQ=None, dEig=None, dVk=None, ws=None):
+    dt, n, m, ld = _cube(Y)
+    if dt != PCA_IN_F32:
+        raise ValueError("pca_backward needs a float32 cube")
+    for name, t, shape in (("mean", mean, (m,)), ("eigvals", eigvals, (m,)), ("V", V, (m, m)),
+                           ("dQ", dQ, (n, k)), ("dEig", dEig, (m,)), ("dVk", dVk, (m, k))):
+        _f32(name, t, shape)
+    if dY.dtype != torch.float32 or dY.dim() != 2 or tuple(dY.shape) != (n, m) or dY.stride(1) != 1:
+        raise ValueError("dY must be a float32 [pixels, bands] device tensor with unit band stride")
+    if ws is None:
+        ws = workspace(pca_workspace_size(PCA_OP_BACKWARD, n, m, k=k), Y.device)
+    _check("pca_backward", _lib().pca_backward(_ptr(Y), n, m, ld, _ptr(mean), _ptr(eigvals), _ptr(V), int(k),
+                                               _ptr(dQ), _ptr(dEig), _ptr(dVk), _ptr(dY), dY.stride(0), _ptr(ws),
+                                               ws.numel(), _stream()))
 
 
 def new_info(device=None) -> torch.Tensor:

@@ -73,3 +73,37 @@ def run(Y: torch.Tensor, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
     """PCA of one device cube Y [pixels, bands] (float32 or uint16)."""
     pipe = PCAPipeline(Y.shape[0], Y.shape[1], k, mode, tol, max_sweeps, fp64_angles, Y.device)
     return pipe.forward(Y)
+
+
+class PCAFunction(torch.autograd.Function):
+    """(Q, eigvals, V[:, :k]) = PCA(Y) with the hand-written adjoint of
+    pca_backward as its derivative. Forward: fused centring + covariance,
+    Jacobi eigenpairs, projection; backward: one pca_backward call."""
+
+    @staticmethod
+    def forward(ctx, Y, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
+                max_sweeps: int = DEFAULT_MAX_SWEEPS):
+        if Y.dtype != torch.float32:
+            raise ValueError("PCAFunction needs a float32 cube")
+        Yc = Y.detach()
+        pipe = PCAPipeline(Yc.shape[0], Yc.shape[1], k, mode, tol, max_sweeps, True, Yc.device)
+        r = pipe.forward(Yc)
+        mean, eigvals, V = r.mean.clone(), r.eigvals.clone(), r.V.clone()
+        ctx.save_for_backward(Yc, mean, eigvals, V)
+        ctx.k = int(k)
+        return r.Q.clone(), eigvals.clone(), V[:, :k].contiguous()
+
+    @staticmethod
+    def backward(ctx, dQ, dEig, dVk):
+        Y, mean, eigvals, V = ctx.saved_tensors
+        k = ctx.k
+        dY = torch.empty_like(Y)
+        prep = lambda t: None if t is None else t.detach().to(torch.float32).contiguous()
+        L.pca_backward(Y, mean, eigvals, V, k, dY, prep(dQ), prep(dEig), prep(dVk))
+        return dY, None, None, None, None
+
+
+def pca_autograd(Y: torch.Tensor, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
+                 max_sweeps: int = DEFAULT_MAX_SWEEPS):
+    """Differentiable PCA of a float32 device cube: returns (Q, eigvals, V_k)."""
+    return PCAFunction.apply(Y, k, mode, tol, max_sweeps)

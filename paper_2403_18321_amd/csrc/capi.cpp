@@ -28,6 +28,7 @@ inline pca_status hip_status(hipError_t e) { return e == hipSuccess ? PCA_OK : P
 size_t center_ws(const pca::CovPlan &p, int m) { return al(p.bytes_sum) + al((size_t)m * sizeof(double)); }
 size_t cov_ws(const pca::CovPlan &p) { return al(p.bytes_S) + al(p.bytes_sum) + al(p.bytes_shift) + al(p.bytes_part2); }
 size_t jac_ws(const pca::JacPlan &p) { return al(p.bytes_log) + al(p.bytes_lam) + al(p.bytes_vu) + al(p.bytes_info); }
+size_t bwd_ws(const pca::BwdPlan &p) { return al(p.bytes_part) + al(p.bytes_w) + al(p.bytes_sums) + al(p.bytes_g); }
 
 }  // namespace
 
@@ -48,7 +49,6 @@ const char *pca_status_string(pca_status s)
 pca_status pca_workspace_size(int op, int64_t n_pixels, int32_t n_bands, int32_t k, int32_t mode,
                               int32_t max_sweeps, size_t *bytes)
 {
-    (void)k;
     if (!bytes || n_bands < 2 || n_bands > pca::kMaxBands) return PCA_ERR_ARG;
     switch (op) {
     case PCA_OP_CENTER:
@@ -65,6 +65,10 @@ pca_status pca_workspace_size(int op, int64_t n_pixels, int32_t n_bands, int32_t
         return PCA_OK;
     case PCA_OP_PROJECT:
         *bytes = 0;
+        return PCA_OK;
+    case PCA_OP_BACKWARD:
+        if (n_pixels < 2 || k < 1 || k > n_bands) return PCA_ERR_ARG;
+        *bytes = bwd_ws(pca::bwd_plan(n_pixels, n_bands, k));
         return PCA_OK;
     default:
         return PCA_ERR_UNSUPPORTED;
@@ -143,6 +147,30 @@ pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands,
     if (!aligned(V, 4) || !aligned(Q, 4) || (mean && !aligned(mean, 4))) return PCA_ERR_ARG;
     return hip_status(pca::launch_project(Y, dt, n_pixels, n_bands, ld_y, mean, V, k, Q,
                                           static_cast<hipStream_t>(stream)));
+}
+
+pca_status pca_backward(const float *Y, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,
+                        const float *eigvals, const float *V, int32_t k, const float *dQ, const float *dEig,
+                        const float *dVk, float *dY, int64_t ld_dy, void *ws, size_t ws_bytes, void *stream)
+{
+    pca_status s = check_cube(Y, PCA_IN_F32, n_pixels, n_bands, ld_y);
+    if (s != PCA_OK) return s;
+    if (!mean || !eigvals || !V || !dY || !ws || k < 1 || k > n_bands || ld_dy < n_bands) return PCA_ERR_ARG;
+    if (!aligned(mean, 4) || !aligned(eigvals, 4) || !aligned(V, 4) || !aligned(dY, 4) || !aligned(ws, kWsAlign))
+        return PCA_ERR_ARG;
+    if ((dQ && !aligned(dQ, 4)) || (dEig && !aligned(dEig, 4)) || (dVk && !aligned(dVk, 4))) return PCA_ERR_ARG;
+    const pca::BwdPlan plan = pca::bwd_plan(n_pixels, n_bands, k);
+    if (ws_bytes < bwd_ws(plan)) return PCA_ERR_WORKSPACE;
+    char *w = static_cast<char *>(ws);
+    double *part = reinterpret_cast<double *>(w);
+    w += al(plan.bytes_part);
+    double *wbuf = reinterpret_cast<double *>(w);
+    w += al(plan.bytes_w);
+    double *sums = reinterpret_cast<double *>(w);
+    w += al(plan.bytes_sums);
+    float *G = reinterpret_cast<float *>(w);
+    return hip_status(pca::launch_backward(Y, n_pixels, n_bands, ld_y, mean, eigvals, V, k, dQ, dEig, dVk, dY, ld_dy,
+                                           plan, part, wbuf, sums, G, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

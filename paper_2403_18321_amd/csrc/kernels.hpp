@@ -54,6 +54,23 @@ struct JacPlan {
 };
 JacPlan jac_plan(int m, int max_sweeps);
 
+// ---- backward ----------------------------------------------------------------
+struct BwdPlan {
+    int kg;              // groups of 8 components
+    int64_t chunk;       // pixels per reduction workgroup
+    int nchunks;
+    size_t bytes_part;   // float64 partial sums per (chunk, group)
+    size_t bytes_w;      // w_j vectors, float64 M x k
+    size_t bytes_sums;   // 1^T X and 1^T Qbar, float64
+    size_t bytes_g;      // augmented GEMM operand, float32 (M + k + 1) x M
+};
+BwdPlan bwd_plan(int64_t n, int m, int k);
+
+hipError_t launch_backward(const float *Y, int64_t n, int m, int64_t ld, const float *mean, const float *lam,
+                           const float *V, int k, const float *dQ, const float *dEig, const float *dVk,
+                           float *dY, int64_t ldd, const BwdPlan &p, double *part, double *wbuf, double *sums,
+                           float *G, hipStream_t st);
+
 hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int fp64_angles,
                          const JacPlan &plan, double *lam_u, float2 *log, float *Vu,
                          pca_info *info_ws, float *eigvals, float *V, pca_info *info_out,

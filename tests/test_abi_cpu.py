@@ -33,7 +33,8 @@ def test_header_symbols_exported(lib):
     so = ctypes.CDLL(lib.LIB_PATH)
     for name in names:
         assert hasattr(so, name), f"{name} declared in pca.h but not exported"
-    assert set(names) <= set(lib.EXPORTS) | {"pca_backward"}
+    assert set(names) <= set(lib.EXPORTS)
+    assert "pca_backward" in names
 
 
 def test_status_strings(lib):
@@ -50,6 +51,10 @@ def test_workspace_sizes(lib):
     j = L.pca_workspace_size(L.PCA_OP_JACOBI, 2, 224, max_sweeps=30)
     assert j >= 30 * 223 * 112 * 8
     assert L.pca_workspace_size(L.PCA_OP_PROJECT, 100, 10) == 0
+    g = L.pca_workspace_size(L.PCA_OP_BACKWARD, 1 << 16, 128, k=8)
+    assert g >= (128 + 8 + 1) * 128 * 4 + 128 * 8 * 8
+    with pytest.raises(L.PCAError):
+        L.pca_workspace_size(L.PCA_OP_BACKWARD, 1 << 16, 128, k=129)
     with pytest.raises(L.PCAError):
         L.pca_workspace_size(L.PCA_OP_COVARIANCE, 100, 257)
     with pytest.raises(L.PCAError):
@@ -80,3 +85,11 @@ def test_invalid_arguments_rejected_on_host(lib):
     # Projection: k out of range.
     assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 0, fake, null) == ARG
     assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 9, fake, null) == ARG
+    # Backward: k out of range, ld_dy < bands, NULL dY, workspace too small.
+    bw = so.pca_backward
+    assert bw(fake, 100, 8, 8, fake, fake, fake, 0, null, null, null, fake, 8, fake, 1 << 20, null) == ARG
+    assert bw(fake, 100, 8, 8, fake, fake, fake, 9, null, null, null, fake, 8, fake, 1 << 20, null) == ARG
+    assert bw(fake, 100, 8, 8, fake, fake, fake, 2, null, null, null, fake, 7, fake, 1 << 20, null) == ARG
+    assert bw(fake, 100, 8, 8, fake, fake, fake, 2, null, null, null, null, 8, fake, 1 << 20, null) == ARG
+    assert bw(fake, 100, 8, 8, fake, fake, fake, 2, fake, null, null, fake, 8, fake, 256,
+              null) == lib.PCA_ERR_WORKSPACE
