@@ -84,6 +84,26 @@ typedef struct {
     int32_t n_bands;
 } pca_info;
 
+/* One cube of a batch (pca_batched). Every pointer is a device pointer. */
+typedef struct {
+    const void *Y;       /* [n_pixels][ld_y] cube, element type given to pca_batched */
+    int64_t n_pixels;    /* >= 2 */
+    int64_t ld_y;        /* >= n_bands */
+    int32_t n_bands;     /* 2 .. 256 */
+    int32_t k;           /* kept components, 1 .. n_bands */
+    float *mean;         /* [n_bands] out */
+    float *eigvals;      /* [n_bands] out, descending */
+    float *V;            /* [n_bands][n_bands] out, column i = eigenvector i */
+    float *Q;            /* [n_pixels][k] out */
+    pca_info *info;      /* out, may be NULL */
+} pca_cube;
+
+/* Tile shapes of the batched launches (0 = default). */
+typedef struct {
+    int32_t cov_chunk;   /* pixels per covariance work item (multiple of 32, <= 16384) */
+    int32_t proj_tiles;  /* 64-pixel tiles per projection work item (>= 1) */
+} pca_batch_tuning;
+
 /* Human-readable name of a status code (static storage). */
 const char *pca_status_string(pca_status s);
 
@@ -189,6 +209,35 @@ pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands,
 pca_status pca_backward(const float *Y, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,
                         const float *eigvals, const float *V, int32_t k, const float *dQ, const float *dEig,
                         const float *dVk, float *dY, int64_t ld_dy, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Workspace bytes of pca_batched for these cubes (host array), covariance
+ * mode, max_sweeps and tuning (NULL = defaults).
+ */
+pca_status pca_batched_workspace_size(const pca_cube *cubes, int32_t n_cubes, int mode, int32_t max_sweeps,
+                                      const pca_batch_tuning *tuning, size_t *bytes);
+
+/*
+ * The whole pipeline (Algorithm 1) for many cubes of different pixel and
+ * band counts, each as pca_covariance + pca_jacobi_eigh + pca_project would
+ * compute it alone, in eight launches for the whole batch: a set-up kernel
+ * that builds the task table in the workspace, one persistent covariance
+ * launch whose workgroups take (cube, pixel chunk) items from a queue,
+ * largest band counts first, the float64 chunk combination, one Jacobi
+ * launch with a workgroup per cube (each cube's rotations on its own CU),
+ * the eigenvector replay, the sort and sign fix, and one projection launch.
+ *   cubes      host array of n_cubes descriptors (validation and sizing).
+ *   cubes_dev  the same array in device memory (read by the set-up kernel;
+ *              keeping it resident makes the sequence capturable in a graph).
+ *   n_cubes    1 .. 4096.
+ *   dt         pca_in_dtype of every cube; mode a pca_cov_mode.
+ *   tol, max_sweeps, fp64_angles  as for pca_jacobi_eigh.
+ *   tuning     tile shapes (NULL = defaults), e.g. from an autotuner.
+ *   ws         workspace of pca_batched_workspace_size(...) bytes.
+ */
+pca_status pca_batched(const pca_cube *cubes, const pca_cube *cubes_dev, int32_t n_cubes, int dt, int mode,
+                       double tol, int32_t max_sweeps, int32_t fp64_angles, const pca_batch_tuning *tuning,
+                       void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

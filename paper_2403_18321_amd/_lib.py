@@ -31,7 +31,20 @@ INFO_BYTES = struct.calcsize(INFO_FORMAT)
 INFO_FIELDS = ("sweeps", "converged", "nonfinite", "floor_hit", "off_rel", "rotations", "steps", "n_bands")
 
 EXPORTS = ("pca_status_string", "pca_workspace_size", "pca_center", "pca_covariance",
-           "pca_jacobi_eigh", "pca_project", "pca_backward")
+           "pca_jacobi_eigh", "pca_project", "pca_backward", "pca_batched_workspace_size", "pca_batched")
+
+
+class PCACube(ctypes.Structure):
+    """struct pca_cube of include/pca.h."""
+    _fields_ = [("Y", ctypes.c_void_p), ("n_pixels", ctypes.c_int64), ("ld_y", ctypes.c_int64),
+                ("n_bands", ctypes.c_int32), ("k", ctypes.c_int32), ("mean", ctypes.c_void_p),
+                ("eigvals", ctypes.c_void_p), ("V", ctypes.c_void_p), ("Q", ctypes.c_void_p),
+                ("info", ctypes.c_void_p)]
+
+
+class PCABatchTuning(ctypes.Structure):
+    """struct pca_batch_tuning of include/pca.h."""
+    _fields_ = [("cov_chunk", ctypes.c_int32), ("proj_tiles", ctypes.c_int32)]
 
 
 class PCAError(RuntimeError):
@@ -66,6 +79,11 @@ def _lib() -> ctypes.CDLL:
         lib.pca_jacobi_eigh.argtypes = [_vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
         lib.pca_project.restype = ctypes.c_int
         lib.pca_project.argtypes = [_vp, ctypes.c_int, _i64, _i32, _i64, _vp, _vp, _i32, _vp, _vp]
+        lib.pca_batched_workspace_size.restype = ctypes.c_int
+        lib.pca_batched_workspace_size.argtypes = [_vp, _i32, ctypes.c_int, _i32, _vp, ctypes.POINTER(_sz)]
+        lib.pca_batched.restype = ctypes.c_int
+        lib.pca_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.c_int, _f64, _i32, _i32, _vp, _vp, _sz,
+                                    _vp]
         lib.pca_backward.restype = ctypes.c_int
         lib.pca_backward.argtypes = [_vp, _i64, _i32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _sz,
                                      _vp]
@@ -174,6 +192,24 @@ def pca_backward(Y, mean, eigvals, V, k: int, dY, dQ=None, dEig=None, dVk=None, 
     _check("pca_backward", _lib().pca_backward(_ptr(Y), n, m, ld, _ptr(mean), _ptr(eigvals), _ptr(V), int(k),
                                                _ptr(dQ), _ptr(dEig), _ptr(dVk), _ptr(dY), dY.stride(0), _ptr(ws),
                                                ws.numel(), _stream()))
+
+
+def pca_batched_workspace_size(cubes_host, n_cubes: int, mode: int, max_sweeps: int, tuning=None) -> int:
+    out = _sz(0)
+    _check("pca_batched_workspace_size",
+           _lib().pca_batched_workspace_size(ctypes.cast(cubes_host, _vp), int(n_cubes), int(mode), int(max_sweeps),
+                                             None if tuning is None else ctypes.cast(ctypes.pointer(tuning), _vp),
+                                             ctypes.byref(out)))
+    return int(out.value)
+
+
+def pca_batched(cubes_host, cubes_dev, n_cubes: int, dt: int, mode: int, tol: float, max_sweeps: int,
+                fp64_angles: bool, tuning, ws):
+    _check("pca_batched",
+           _lib().pca_batched(ctypes.cast(cubes_host, _vp), _ptr(cubes_dev), int(n_cubes), int(dt), int(mode),
+                              float(tol), int(max_sweeps), int(bool(fp64_angles)),
+                              None if tuning is None else ctypes.cast(ctypes.pointer(tuning), _vp), _ptr(ws),
+                              ws.numel(), _stream()))
 
 
 def new_info(device=None) -> torch.Tensor:

@@ -30,6 +30,46 @@ size_t cov_ws(const pca::CovPlan &p) { return al(p.bytes_S) + al(p.bytes_sum) + 
 size_t jac_ws(const pca::JacPlan &p) { return al(p.bytes_log) + al(p.bytes_lam) + al(p.bytes_vu) + al(p.bytes_info); }
 size_t bwd_ws(const pca::BwdPlan &p) { return al(p.bytes_part) + al(p.bytes_w) + al(p.bytes_sums) + al(p.bytes_g); }
 
+// Host-side checks and sizes of a batch; fills the six launch totals.
+pca_status batch_plan(const pca_cube *cubes, int32_t n_cubes, int32_t max_sweeps, const pca_batch_tuning *tuning,
+                      int dt, size_t *bytes, int64_t total[6], int *max_k, int *cov_chunk, int *proj_tiles)
+{
+    if (!cubes || n_cubes < 1 || n_cubes > 4096 || max_sweeps < 0 || max_sweeps > 100000) return PCA_ERR_ARG;
+    int chunk = pca::kBatchDefaultChunk, tiles = pca::kBatchDefaultTiles;
+    if (tuning) {
+        if (tuning->cov_chunk < 0 || tuning->cov_chunk > pca::kCovMaxChunk || tuning->cov_chunk % pca::kCovTile)
+            return PCA_ERR_ARG;
+        if (tuning->proj_tiles < 0 || tuning->proj_tiles > 4096) return PCA_ERR_ARG;
+        if (tuning->cov_chunk) chunk = tuning->cov_chunk;
+        if (tuning->proj_tiles) tiles = tuning->proj_tiles;
+    }
+    size_t b = pca::batch_table_bytes(n_cubes);
+    for (int q = 0; q < 6; ++q) total[q] = 0;
+    int mk = 1;
+    for (int32_t i = 0; i < n_cubes; ++i) {
+        const pca_cube &c = cubes[i];
+        pca_status s = check_cube(c.Y, dt, c.n_pixels, c.n_bands, c.ld_y);
+        if (s != PCA_OK) return s;
+        if (c.k < 1 || c.k > c.n_bands || !c.mean || !c.eigvals || !c.V || !c.Q) return PCA_ERR_ARG;
+        if (!aligned(c.mean, 4) || !aligned(c.eigvals, 4) || !aligned(c.V, 4) || !aligned(c.Q, 4)) return PCA_ERR_ARG;
+        if (c.info && !aligned(c.info, 8)) return PCA_ERR_ARG;
+        const pca::CovPlan cp = pca::cov_plan_chunk(c.n_pixels, c.n_bands, chunk);
+        const pca::JacPlan jp = pca::jac_plan(c.n_bands, max_sweeps);
+        b += pca::batch_cube_bytes(cp, jp, c.n_bands);
+        int64_t cnt[6];
+        pca::batch_counts(cp, c.n_pixels, c.n_bands, tiles, cnt);
+        for (int q = 0; q < 6; ++q) total[q] += cnt[q];
+        if (c.k > mk) mk = c.k;
+    }
+    for (int q = 0; q < 6; ++q)
+        if (total[q] > 0x7fffffffLL) return PCA_ERR_UNSUPPORTED;
+    *bytes = b;
+    if (max_k) *max_k = mk;
+    if (cov_chunk) *cov_chunk = chunk;
+    if (proj_tiles) *proj_tiles = tiles;
+    return PCA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -171,6 +211,39 @@ pca_status pca_backward(const float *Y, int64_t n_pixels, int32_t n_bands, int64
     float *G = reinterpret_cast<float *>(w);
     return hip_status(pca::launch_backward(Y, n_pixels, n_bands, ld_y, mean, eigvals, V, k, dQ, dEig, dVk, dY, ld_dy,
                                            plan, part, wbuf, sums, G, static_cast<hipStream_t>(stream)));
+}
+
+pca_status pca_batched_workspace_size(const pca_cube *cubes, int32_t n_cubes, int mode, int32_t max_sweeps,
+                                      const pca_batch_tuning *tuning, size_t *bytes)
+{
+    if (!bytes || mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
+    int64_t total[6];
+    // The element type does not change the sizes; check the cube pointers at
+    // the weaker (uint16) alignment here, pca_batched checks them again.
+    return batch_plan(cubes, n_cubes, max_sweeps, tuning, PCA_IN_U16, bytes, total, nullptr, nullptr, nullptr);
+}
+
+pca_status pca_batched(const pca_cube *cubes, const pca_cube *cubes_dev, int32_t n_cubes, int dt, int mode,
+                       double tol, int32_t max_sweeps, int32_t fp64_angles, const pca_batch_tuning *tuning,
+                       void *ws, size_t ws_bytes, void *stream)
+{
+    if (!cubes_dev || !aligned(cubes_dev, 8) || !ws || !aligned(ws, kWsAlign) || !valid_dt(dt)) return PCA_ERR_ARG;
+    if (mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
+    if (!(tol >= 0.0) || !isfinite(tol) || (fp64_angles != 0 && fp64_angles != 1)) return PCA_ERR_ARG;
+    size_t need = 0;
+    int64_t total[6];
+    int max_k = 1, chunk = 0, tiles = 0;
+    pca_status s = batch_plan(cubes, n_cubes, max_sweeps, tuning, dt, &need, total, &max_k, &chunk, &tiles);
+    if (s != PCA_OK) return s;
+    if (ws_bytes < need) return PCA_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    if (pca::launch_batch_setup(cubes_dev, n_cubes, mode, max_sweeps, chunk, tiles, w, st) != hipSuccess)
+        return PCA_ERR_HIP;
+    if (pca::launch_cov_batched(dt, mode, w, total, n_cubes, st) != hipSuccess) return PCA_ERR_HIP;
+    if (pca::launch_jacobi_batched(w, total, n_cubes, tol, max_sweeps, fp64_angles, st) != hipSuccess)
+        return PCA_ERR_HIP;
+    return hip_status(pca::launch_project_batched(dt, w, total, n_cubes, max_k, st));
 }
 
 }  // extern "C"

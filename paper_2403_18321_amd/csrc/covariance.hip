@@ -47,10 +47,13 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
     lo = (__bf16)(x - (float)hi);
 }
 
+// One chunk c of one cube (the body of the single-cube and the batched
+// launches).
 template <typename T, int VEC, int MODE>
-__global__ __launch_bounds__(kThreads) void cov_partial_kernel(
+__device__ __forceinline__ void cov_partial_body(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
-    int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+    int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
+    int64_t c)
 {
     constexpr int kF32Max = KT * (256 + 32);
     constexpr int kBfMax = 256 * kBfPitch;
@@ -62,7 +65,6 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t c = blockIdx.x;
     const int64_t pbeg = c * chunk;
     const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
     const int pf = f32_pitch(mpad);
@@ -261,13 +263,22 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
     }
 }
 
+template <typename T, int VEC, int MODE>
+__global__ __launch_bounds__(kThreads) void cov_partial_kernel(
+    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
+    int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+{
+    cov_partial_body<T, VEC, MODE>(Y, n, m, ld, centered, chunk, nb, nblk, mpad, partS, partSum, partShift,
+                                   (int64_t)blockIdx.x);
+}
+
 // Pass 2a: grid (block, chunk group). Every workgroup forms the band means of
 // its block's 64 bands (all chunks, float64, fixed order: identical in every
 // workgroup), then the centred second moment of its range of chunks.
-__global__ __launch_bounds__(1024) void cov_finalize_part_kernel(
+__device__ __forceinline__ void cov_finalize_part_body(
     int64_t n, int m, int centered, int64_t chunk, int64_t nchunks, int nb, int nblk, int mpad,
     const float *__restrict__ partS, const double *__restrict__ partSum, const float *__restrict__ partShift,
-    double *__restrict__ part2)
+    double *__restrict__ part2, int e, int gi, int G)
 {
     constexpr int kBatch = 32;
     __shared__ double mu[64];
@@ -275,7 +286,6 @@ __global__ __launch_bounds__(1024) void cov_finalize_part_kernel(
     __shared__ float shv[kBatch][64];
     __shared__ double smv[kBatch][64];
 
-    const int e = blockIdx.x, gi = blockIdx.y, G = gridDim.y;
     int bi = 0, rem = e;
     while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
     const int bj = bi + rem;
@@ -342,12 +352,20 @@ __global__ __launch_bounds__(1024) void cov_finalize_part_kernel(
     if (gi == 0 && bi == bj && tid < 32) part2[(int64_t)G * nblk * 1024 + 1 + 32 * bi + tid] = mu[tid];
 }
 
-// Pass 2b: the chunk groups added in order, divided by N - 1, mirrored.
-__global__ __launch_bounds__(1024) void cov_finalize_sum_kernel(int64_t n, int m, int centered, int nb, int nblk,
-                                                                int G, const double *__restrict__ part2,
-                                                                float *__restrict__ C, float *__restrict__ mean)
+__global__ __launch_bounds__(1024) void cov_finalize_part_kernel(
+    int64_t n, int m, int centered, int64_t chunk, int64_t nchunks, int nb, int nblk, int mpad,
+    const float *__restrict__ partS, const double *__restrict__ partSum, const float *__restrict__ partShift,
+    double *__restrict__ part2)
 {
-    const int e = blockIdx.x;
+    cov_finalize_part_body(n, m, centered, chunk, nchunks, nb, nblk, mpad, partS, partSum, partShift, part2,
+                           (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.y);
+}
+
+// Pass 2b: the chunk groups added in order, divided by N - 1, mirrored.
+__device__ __forceinline__ void cov_finalize_sum_body(int64_t n, int m, int centered, int nb, int nblk, int G,
+                                             const double *__restrict__ part2, float *__restrict__ C,
+                                             float *__restrict__ mean, int e)
+{
     int bi = 0, rem = e;
     while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
     const int bj = bi + rem;
@@ -365,6 +383,74 @@ __global__ __launch_bounds__(1024) void cov_finalize_sum_kernel(int64_t n, int m
     }
     if (mean && !centered && bi == bj && tid < 32 && 32 * bi + tid < m)
         mean[32 * bi + tid] = (float)part2[(int64_t)G * nblk * 1024 + 1 + 32 * bi + tid];
+}
+
+__global__ __launch_bounds__(1024) void cov_finalize_sum_kernel(int64_t n, int m, int centered, int nb, int nblk,
+                                                                int G, const double *__restrict__ part2,
+                                                                float *__restrict__ C, float *__restrict__ mean)
+{
+    cov_finalize_sum_body(n, m, centered, nb, nblk, G, part2, C, mean, (int)blockIdx.x);
+}
+
+// ---- batched form: task table in the workspace (see kernels.hpp) ----------
+__device__ inline const BatchCube *batch_table(const char *ws)
+{
+    return reinterpret_cast<const BatchCube *>(ws + sizeof(BatchHeader));
+}
+
+// Cube whose range of work items [w, w + count) holds `item` (entries are
+// sorted by their first item).
+template <int64_t BatchCube::*W>
+__device__ inline int batch_find(const BatchCube *t, int nc, int64_t item)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (t[mid].*W <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Persistent: workgroups take (cube, chunk) items from a queue until it is
+// empty; each item's results land in fixed slots, so the order in which
+// items are taken does not change them.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void cov_partial_batched_kernel(char *ws, int nc, int64_t total)
+{
+    __shared__ int64_t item_sh;
+    BatchHeader *h = reinterpret_cast<BatchHeader *>(ws);
+    const BatchCube *t = batch_table(ws);
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&h->counter[0], 1u);
+        __syncthreads();
+        const int64_t item = item_sh;
+        if (item >= total) break;
+        const BatchCube &cb = t[batch_find<&BatchCube::w_cov>(t, nc, item)];
+        cov_partial_body<T, 1, MODE>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, 0, cb.cov.chunk, cb.cov.nb,
+                                     cb.cov.nblk, cb.cov.mpad, cb.partS, cb.partSum, cb.partShift, item - cb.w_cov);
+    }
+}
+
+__global__ __launch_bounds__(1024) void cov_finalize_part_batched_kernel(const char *ws, int nc)
+{
+    const BatchCube *t = batch_table(ws);
+    const int64_t item = blockIdx.x;
+    const BatchCube &cb = t[batch_find<&BatchCube::w_fin1>(t, nc, item)];
+    const int64_t local = item - cb.w_fin1;
+    cov_finalize_part_body(cb.n, cb.m, 0, cb.cov.chunk, cb.cov.nchunks, cb.cov.nb, cb.cov.nblk, cb.cov.mpad, cb.partS,
+                           cb.partSum, cb.partShift, cb.part2, (int)(local % cb.cov.nblk), (int)(local / cb.cov.nblk),
+                           cb.cov.groups);
+}
+
+__global__ __launch_bounds__(1024) void cov_finalize_sum_batched_kernel(const char *ws, int nc)
+{
+    const BatchCube *t = batch_table(ws);
+    const int64_t item = blockIdx.x;
+    const BatchCube &cb = t[batch_find<&BatchCube::w_fin2>(t, nc, item)];
+    cov_finalize_sum_body(cb.n, cb.m, 0, cb.cov.nb, cb.cov.nblk, cb.cov.groups, cb.part2, cb.C, cb.mean,
+                          (int)(item - cb.w_fin2));
 }
 
 template <typename T, int VEC>
@@ -435,6 +521,34 @@ hipError_t launch_cov_finalize(int64_t n, int m, int centered, const CovPlan &pl
                        partShift, part2);
     hipLaunchKernelGGL(cov_finalize_sum_kernel, dim3((unsigned)plan.nblk), dim3(1024), 0, st, n, m, centered,
                        plan.nb, plan.nblk, plan.groups, (const double *)part2, C, mean);
+    return hipGetLastError();
+}
+
+hipError_t launch_cov_batched(int dt, int mode, const char *ws, const int64_t total[6], int n_cubes, hipStream_t st)
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    int64_t g = (int64_t)cus * 2;
+    if (g > total[0]) g = total[0];
+    if (g < 1) g = 1;
+    char *w = const_cast<char *>(ws);
+    const dim3 grid((unsigned)g), block(kThreads);
+#define PCA_COV_B(T, M)                                                                                           \
+    hipLaunchKernelGGL((cov_partial_batched_kernel<T, M>), grid, block, 0, st, w, n_cubes, total[0])
+    if (dt == PCA_IN_F32) {
+        if (mode == MODE_F32) PCA_COV_B(float, MODE_F32);
+        else if (mode == MODE_BF16X3) PCA_COV_B(float, MODE_BF16X3);
+        else PCA_COV_B(float, MODE_BF16X4);
+    } else {
+        if (mode == MODE_F32) PCA_COV_B(uint16_t, MODE_F32);
+        else if (mode == MODE_BF16X3) PCA_COV_B(uint16_t, MODE_BF16X3);
+        else PCA_COV_B(uint16_t, MODE_BF16X4);
+    }
+#undef PCA_COV_B
+    hipLaunchKernelGGL(cov_finalize_part_batched_kernel, dim3((unsigned)total[1]), dim3(1024), 0, st, ws, n_cubes);
+    hipLaunchKernelGGL(cov_finalize_sum_batched_kernel, dim3((unsigned)total[2]), dim3(1024), 0, st, ws, n_cubes);
     return hipGetLastError();
 }
 

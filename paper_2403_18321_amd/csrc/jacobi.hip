@@ -227,10 +227,9 @@ __device__ inline int block_sum_i(int v, int *red)
 //   thread j < P moves pair j's rotated pivot to its next place and logs the
 //     rotation.
 template <int L>
-__global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restrict__ C, int m, int n, double tol,
-                                                           int max_sweeps, int fp64_angles,
-                                                           double *__restrict__ lam_u, float2 *__restrict__ rlog,
-                                                           pca_info *__restrict__ info)
+__device__ __forceinline__ void jacobi_body(const float *__restrict__ C, int m, int n, double tol, int max_sweeps,
+                                   int fp64_angles, double *__restrict__ lam_u, float2 *__restrict__ rlog,
+                                   pca_info *__restrict__ info)
 {
     __shared__ float4 blk[kMaxRowBlocks + kBlockPad];
     __shared__ double dg[2][256];
@@ -521,6 +520,15 @@ __global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restri
     }
 }
 
+template <int L>
+__global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restrict__ C, int m, int n, double tol,
+                                                           int max_sweeps, int fp64_angles,
+                                                           double *__restrict__ lam_u, float2 *__restrict__ rlog,
+                                                           pca_info *__restrict__ info)
+{
+    jacobi_body<L>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info);
+}
+
 constexpr int kReplayThreads = 512;
 constexpr int kReplayMaxRows = 8;
 constexpr int kReplayBatch = 16;
@@ -529,9 +537,8 @@ constexpr int kReplayPre = (kReplayBatch * kMaxP + kReplayThreads - 1) / kReplay
 // Rows r0 .. r0+R-1 of the eigenvector matrix, in slot coordinates,
 // double-buffered: thread (r, k) rotates columns (T_k, B_k) of row r and
 // writes them to their permuted places, one barrier per step.
-__global__ __launch_bounds__(kReplayThreads) void vreplay_kernel(int n, int rows, const float2 *__restrict__ rlog,
-                                                                  const pca_info *__restrict__ info,
-                                                                  float *__restrict__ VuT)
+__device__ __forceinline__ void vreplay_body(int n, int rows, const float2 *__restrict__ rlog,
+                                    const pca_info *__restrict__ info, float *__restrict__ VuT, int wg)
 {
     __shared__ float vb[2][kReplayMaxRows][256];
     __shared__ float2 lcs[2][kReplayBatch][kMaxP];
@@ -539,7 +546,7 @@ __global__ __launch_bounds__(kReplayThreads) void vreplay_kernel(int n, int rows
     S.init(n, nullptr, nullptr);
     const int P = S.P;
     const int tid = threadIdx.x;
-    const int r0 = blockIdx.x * rows;
+    const int r0 = wg * rows;
     const int nsteps = info->steps;
     const int per = kReplayBatch * P;
 
@@ -595,22 +602,27 @@ __global__ __launch_bounds__(kReplayThreads) void vreplay_kernel(int n, int rows
     }
 }
 
+__global__ __launch_bounds__(kReplayThreads) void vreplay_kernel(int n, int rows, const float2 *__restrict__ rlog,
+                                                                  const pca_info *__restrict__ info,
+                                                                  float *__restrict__ VuT)
+{
+    vreplay_body(n, rows, rlog, info, VuT, (int)blockIdx.x);
+}
+
 // One wave per output column: rank by counting (stable, descending), then the
 // sign from the column's largest-magnitude entry (lowest row on ties).
-__global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const double *__restrict__ lam_u,
-                                                        const float *__restrict__ VuT,
-                                                        const pca_info *__restrict__ info_ws,
-                                                        float *__restrict__ eigvals, float *__restrict__ V,
-                                                        pca_info *__restrict__ info_out)
+__device__ __forceinline__ void sort_sign_body(int m, int n, const double *__restrict__ lam_u, const float *__restrict__ VuT,
+                                      const pca_info *__restrict__ info_ws, float *__restrict__ eigvals,
+                                      float *__restrict__ V, pca_info *__restrict__ info_out, int wg)
 {
     __shared__ int perm[256];
     __shared__ double lam[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int c = blockIdx.x * 4 + wave;
+    const int c = wg * 4 + wave;
     if (info_ws->nonfinite) {
-        if (blockIdx.x == 0) for (int i = tid; i < m; i += 256) eigvals[i] = NAN;
+        if (wg == 0) for (int i = tid; i < m; i += 256) eigvals[i] = NAN;
         if (c < m) for (int r = lane; r < m; r += 64) V[(int64_t)r * m + c] = NAN;
-        if (blockIdx.x == 0 && tid == 0 && info_out) *info_out = *info_ws;
+        if (wg == 0 && tid == 0 && info_out) *info_out = *info_ws;
         return;
     }
     if (tid < m) lam[tid] = lam_u[tid];
@@ -623,7 +635,7 @@ __global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const doub
             rank += (y > x) || (y == x && j < tid);
         }
         perm[rank] = tid;
-        if (blockIdx.x == 0) eigvals[rank] = (float)x;
+        if (wg == 0) eigvals[rank] = (float)x;
     }
     __syncthreads();
     if (c < m) {
@@ -652,7 +664,61 @@ __global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const doub
             if (r < m) V[(int64_t)r * m + c] = sgn * v[i];
         }
     }
-    if (blockIdx.x == 0 && tid == 0 && info_out) *info_out = *info_ws;
+    if (wg == 0 && tid == 0 && info_out) *info_out = *info_ws;
+}
+
+__global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const double *__restrict__ lam_u,
+                                                        const float *__restrict__ VuT,
+                                                        const pca_info *__restrict__ info_ws,
+                                                        float *__restrict__ eigvals, float *__restrict__ V,
+                                                        pca_info *__restrict__ info_out)
+{
+    sort_sign_body(m, n, lam_u, VuT, info_ws, eigvals, V, info_out, (int)blockIdx.x);
+}
+
+// ---- batched form ------------------------------------------------------------
+constexpr int kBatchL = 19;   // segment length that fits every band count
+
+__device__ inline const BatchCube *jbatch_table(const char *ws)
+{
+    return reinterpret_cast<const BatchCube *>(ws + sizeof(BatchHeader));
+}
+
+template <int64_t BatchCube::*W>
+__device__ inline int jbatch_find(const BatchCube *t, int nc, int64_t item)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (t[mid].*W <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One workgroup (one CU) per cube.
+__global__ __launch_bounds__(kJThreads) void jacobi_batched_kernel(const char *ws, double tol, int max_sweeps,
+                                                                   int fp64_angles)
+{
+    const BatchCube &cb = jbatch_table(ws)[blockIdx.x];
+    jacobi_body<kBatchL>(cb.C, cb.m, cb.m + (cb.m & 1), tol, max_sweeps, fp64_angles, cb.lam_u, cb.rlog, cb.info_ws);
+}
+
+__global__ __launch_bounds__(kReplayThreads) void vreplay_batched_kernel(const char *ws, int nc)
+{
+    const BatchCube *t = jbatch_table(ws);
+    const int64_t item = blockIdx.x;
+    const BatchCube &cb = t[jbatch_find<&BatchCube::w_rep>(t, nc, item)];
+    vreplay_body(cb.m + (cb.m & 1), cb.rows, cb.rlog, cb.info_ws, cb.Vu, (int)(item - cb.w_rep));
+}
+
+__global__ __launch_bounds__(256) void sort_sign_batched_kernel(const char *ws, int nc)
+{
+    const BatchCube *t = jbatch_table(ws);
+    const int64_t item = blockIdx.x;
+    const BatchCube &cb = t[jbatch_find<&BatchCube::w_sort>(t, nc, item)];
+    sort_sign_body(cb.m, cb.m + (cb.m & 1), cb.lam_u, cb.Vu, cb.info_ws, cb.eigvals, cb.V, cb.info,
+                   (int)(item - cb.w_sort));
 }
 
 template <int L>
@@ -672,19 +738,6 @@ int jac_segments(int P, int L)
 }
 
 }  // namespace
-
-JacPlan jac_plan(int m, int max_sweeps)
-{
-    JacPlan p;
-    p.me = m + (m & 1);
-    p.npairs = p.me / 2;
-    p.log_steps = (int64_t)(max_sweeps > 0 ? max_sweeps : 0) * (p.me - 1);
-    p.bytes_log = (size_t)(p.log_steps > 0 ? p.log_steps : 1) * p.npairs * sizeof(float2);
-    p.bytes_lam = (size_t)p.me * sizeof(double);
-    p.bytes_vu = (size_t)p.me * p.me * sizeof(float);
-    p.bytes_info = sizeof(pca_info);
-    return p;
-}
 
 hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int fp64_angles, const JacPlan &plan,
                          double *lam_u, float2 *rlog, float *Vu, pca_info *info_ws, float *eigvals, float *V,
@@ -708,13 +761,22 @@ hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int 
     case 17: launch_jac<17>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
     default: launch_jac<19>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
     }
-    int rows = kReplayThreads / P;
-    if (rows > kReplayMaxRows) rows = kReplayMaxRows;
+    const int rows = replay_rows(n);
     const unsigned nwg = (unsigned)((n + rows - 1) / rows);
     hipLaunchKernelGGL(vreplay_kernel, dim3(nwg), dim3(kReplayThreads), 0, st, n, rows, rlog,
                        (const pca_info *)info_ws, Vu);
     hipLaunchKernelGGL(sort_sign_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, m, n,
                        (const double *)lam_u, (const float *)Vu, (const pca_info *)info_ws, eigvals, V, info_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_batched(const char *ws, const int64_t total[6], int n_cubes, double tol, int max_sweeps,
+                                 int fp64_angles, hipStream_t st)
+{
+    hipLaunchKernelGGL(jacobi_batched_kernel, dim3((unsigned)n_cubes), dim3(kJThreads), 0, st, ws, tol, max_sweeps,
+                       fp64_angles);
+    hipLaunchKernelGGL(vreplay_batched_kernel, dim3((unsigned)total[3]), dim3(kReplayThreads), 0, st, ws, n_cubes);
+    hipLaunchKernelGGL(sort_sign_batched_kernel, dim3((unsigned)total[4]), dim3(256), 0, st, ws, n_cubes);
     return hipGetLastError();
 }
 

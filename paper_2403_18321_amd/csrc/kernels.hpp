@@ -30,6 +30,27 @@ struct CovPlan {
 };
 CovPlan cov_plan(int64_t n, int m);
 
+// Plan for a given chunk length (rounded to whole 32-pixel stages, at most
+// kCovMaxChunk); the single-cube plan picks the chunk from N.
+__host__ __device__ inline CovPlan cov_plan_chunk(int64_t n, int m, int64_t chunk)
+{
+    CovPlan p;
+    int64_t c = (chunk + kCovTile - 1) / kCovTile * kCovTile;
+    if (c < kCovTile) c = kCovTile;
+    if (c > kCovMaxChunk) c = kCovMaxChunk;
+    p.chunk = c;
+    p.nchunks = (n + p.chunk - 1) / p.chunk;
+    p.mpad = (m + 31) / 32 * 32;
+    p.nb = p.mpad / 32;
+    p.nblk = p.nb * (p.nb + 1) / 2;
+    p.bytes_S = (size_t)p.nchunks * p.nblk * 1024 * sizeof(float);
+    p.bytes_sum = (size_t)p.nchunks * p.mpad * sizeof(double);
+    p.bytes_shift = (size_t)p.nchunks * p.mpad * sizeof(float);
+    p.groups = (int)(p.nchunks < 8 ? p.nchunks : 8);
+    p.bytes_part2 = ((size_t)p.groups * p.nblk * 1024 + 1 + 256) * sizeof(double);
+    return p;
+}
+
 hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
                               int mode, const CovPlan &plan, float *partS, double *partSum,
                               float *partShift, hipStream_t st);
@@ -52,7 +73,96 @@ struct JacPlan {
     size_t bytes_vu;     // unsorted eigenvectors, float32 me x me
     size_t bytes_info;   // internal pca_info
 };
-JacPlan jac_plan(int m, int max_sweeps);
+__host__ __device__ inline JacPlan jac_plan(int m, int max_sweeps)
+{
+    JacPlan p;
+    p.me = m + (m & 1);
+    p.npairs = p.me / 2;
+    p.log_steps = (int64_t)(max_sweeps > 0 ? max_sweeps : 0) * (p.me - 1);
+    p.bytes_log = (size_t)(p.log_steps > 0 ? p.log_steps : 1) * p.npairs * 2 * sizeof(float);
+    p.bytes_lam = (size_t)p.me * sizeof(double);
+    p.bytes_vu = (size_t)p.me * p.me * sizeof(float);
+    p.bytes_info = sizeof(pca_info);
+    return p;
+}
+
+// Eigenvector-replay rows per workgroup.
+__host__ __device__ inline int replay_rows(int me)
+{
+    const int r = 512 / (me / 2);
+    return r > 8 ? 8 : r;
+}
+
+// ---- batched form ----------------------------------------------------------
+constexpr size_t kBatchAlign = 256;
+__host__ __device__ inline size_t batch_al(size_t x) { return (x + kBatchAlign - 1) / kBatchAlign * kBatchAlign; }
+constexpr int kBatchDefaultChunk = 8192;   // pixels per covariance work item
+constexpr int kBatchDefaultTiles = 16;     // 64-pixel tiles per projection work item
+constexpr int kProjTile = 64;
+
+// Per-cube entry of the device task table (written by the set-up kernel from
+// the caller's descriptors, in decreasing order of work).
+struct BatchCube {
+    const void *Y;
+    int64_t n, ld;
+    int m, k;
+    float *mean, *eigvals, *V, *Q;
+    pca_info *info;
+    CovPlan cov;
+    float *partS;
+    double *partSum;
+    float *partShift;
+    double *part2;
+    float *C;
+    float2 *rlog;
+    double *lam_u;
+    float *Vu;
+    pca_info *info_ws;
+    int rows;              // eigenvector-replay rows per workgroup
+    int proj_tiles;        // 64-pixel tiles per projection work item
+    // First global work item of this cube in each batched launch.
+    int64_t w_cov, w_fin1, w_fin2, w_rep, w_sort, w_proj;
+};
+
+struct BatchHeader {
+    int n_cubes;
+    int pad;
+    int64_t total[6];      // work items of each batched launch
+    unsigned int counter[4];
+};
+
+// Work items of each launch for one cube.
+__host__ __device__ inline void batch_counts(const CovPlan &cp, int64_t n, int m, int tiles, int64_t w[6])
+{
+    const int me = m + (m & 1);
+    w[0] = cp.nchunks;
+    w[1] = (int64_t)cp.nblk * cp.groups;
+    w[2] = cp.nblk;
+    w[3] = (me + replay_rows(me) - 1) / replay_rows(me);
+    w[4] = (m + 3) / 4;
+    w[5] = ((n + kProjTile - 1) / kProjTile + tiles - 1) / tiles;
+}
+
+// Workspace bytes of one cube (after the table).
+__host__ __device__ inline size_t batch_cube_bytes(const CovPlan &cp, const JacPlan &jp, int m)
+{
+    return batch_al(cp.bytes_S) + batch_al(cp.bytes_sum) + batch_al(cp.bytes_shift) + batch_al(cp.bytes_part2) +
+           batch_al((size_t)m * m * sizeof(float)) + batch_al(jp.bytes_log) + batch_al(jp.bytes_lam) +
+           batch_al(jp.bytes_vu) + batch_al(jp.bytes_info);
+}
+
+__host__ __device__ inline size_t batch_table_bytes(int n_cubes)
+{
+    return batch_al(sizeof(BatchHeader) + (size_t)n_cubes * sizeof(BatchCube));
+}
+
+hipError_t launch_batch_setup(const pca_cube *cubes_dev, int n_cubes, int mode, int max_sweeps, int cov_chunk,
+                              int proj_tiles, char *ws, hipStream_t st);
+hipError_t launch_cov_batched(int dt, int mode, const char *ws, const int64_t total[6], int n_cubes, hipStream_t st);
+hipError_t launch_jacobi_batched(const char *ws, const int64_t total[6], int n_cubes, double tol, int max_sweeps,
+                                 int fp64_angles, hipStream_t st);
+hipError_t launch_project_batched(int dt, const char *ws, const int64_t total[6], int n_cubes, int max_k,
+                                  hipStream_t st);
 
 // ---- backward ----------------------------------------------------------------
 struct BwdPlan {

@@ -26,11 +26,11 @@ constexpr int kWGPerCU = 2;
 // bands read by one MFMA operand load hit 64 distinct LDS banks.
 __host__ __device__ inline int proj_pitch(int m4) { return ((m4 / 4) & 1) ? m4 : m4 + 4; }
 
+// Tiles t0, t0 + tstep, ... (< tend) of one cube, component group g.
 template <typename T, int VEC>
-__global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__ Y, int64_t n, int m,
-                                                           int64_t ld, const float *__restrict__ mean,
-                                                           const float *__restrict__ V, int k,
-                                                           float *__restrict__ Q)
+__device__ __forceinline__ void project_body(const T *__restrict__ Y, int64_t n, int m, int64_t ld,
+                                    const float *__restrict__ mean, const float *__restrict__ V, int k,
+                                    float *__restrict__ Q, int64_t t0, int64_t tstep, int64_t tend, int g)
 {
     __shared__ __attribute__((aligned(16))) float tile[kTP * 260];
     __shared__ float mu[256];
@@ -38,8 +38,7 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__
     const int m4 = round_up(m, 4);
     const int pitch = proj_pitch(m4);
     const int ksteps = m4 / 4;
-    const int g = blockIdx.y;
-    const int64_t ntiles = (n + kTP - 1) / kTP;
+    const int64_t ntiles = tend;
 
     for (int b = tid; b < 256; b += kThreads) mu[b] = (mean && b < m) ? mean[b] : 0.f;
 
@@ -57,13 +56,13 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__
 
     // Wave w loads pixel groups w and w + 4 (8 pixels each) of a tile.
     Group<T, VEC> v0, v1;
-    int64_t t = blockIdx.x;
+    int64_t t = t0;
     if (t < ntiles) {
         v0.load(Y, ld, t * kTP + 8 * wave, n, m, lane);
         v1.load(Y, ld, t * kTP + 8 * (wave + 4), n, m, lane);
     }
     const float *arow = &tile[(16 * wave + (lane & 15)) * pitch + (lane >> 4)];
-    for (; t < ntiles; t += gridDim.x) {
+    for (; t < ntiles; t += tstep) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int grp = wave + 4 * h;
@@ -95,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__
         __syncthreads();
 
         // Next tile's loads overlap this tile's products.
-        const int64_t tn = t + gridDim.x;
+        const int64_t tn = t + tstep;
         if (tn < ntiles) {
             v0.load(Y, ld, tn * kTP + 8 * wave, n, m, lane);
             v1.load(Y, ld, tn * kTP + 8 * (wave + 4), n, m, lane);
@@ -118,6 +117,38 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__
         }
         __syncthreads();
     }
+}
+
+template <typename T, int VEC>
+__global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__ Y, int64_t n, int m,
+                                                           int64_t ld, const float *__restrict__ mean,
+                                                           const float *__restrict__ V, int k,
+                                                           float *__restrict__ Q)
+{
+    project_body<T, VEC>(Y, n, m, ld, mean, V, k, Q, (int64_t)blockIdx.x, (int64_t)gridDim.x, (n + kTP - 1) / kTP,
+                         (int)blockIdx.y);
+}
+
+// Batched: one work item = a run of tiles of one cube; blockIdx.y = the
+// 16-component group (workgroups beyond a cube's k return at once).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void project_batched_kernel(const char *ws, int nc)
+{
+    const BatchCube *t = reinterpret_cast<const BatchCube *>(ws + sizeof(BatchHeader));
+    const int64_t item = blockIdx.x;
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (t[mid].w_proj <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchCube &cb = t[lo];
+    const int g = blockIdx.y;
+    if (16 * g >= cb.k) return;
+    const int64_t ntiles = (cb.n + kTP - 1) / kTP;
+    const int64_t t0 = (item - cb.w_proj) * cb.proj_tiles;
+    const int64_t t1 = (t0 + cb.proj_tiles < ntiles) ? t0 + cb.proj_tiles : ntiles;
+    project_body<T, 1>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, cb.mean, cb.V, cb.k, cb.Q, t0, 1, t1, g);
 }
 
 int num_cus()
@@ -155,6 +186,17 @@ hipError_t launch_project(const void *Y, int dt, int64_t n, int m, int64_t ld, c
     const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32) return launch_t(static_cast<const float *>(Y), n, m, ld, mean, V, k, Q, st, v4);
     return launch_t(static_cast<const uint16_t *>(Y), n, m, ld, mean, V, k, Q, st, v4);
+}
+
+hipError_t launch_project_batched(int dt, const char *ws, const int64_t total[6], int n_cubes, int max_k,
+                                  hipStream_t st)
+{
+    const dim3 grid((unsigned)total[5], (unsigned)((max_k + 15) / 16)), block(kThreads);
+    if (dt == PCA_IN_F32)
+        hipLaunchKernelGGL(project_batched_kernel<float>, grid, block, 0, st, ws, n_cubes);
+    else
+        hipLaunchKernelGGL(project_batched_kernel<uint16_t>, grid, block, 0, st, ws, n_cubes);
+    return hipGetLastError();
 }
 
 }  // namespace pca

@@ -93,3 +93,33 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert bw(fake, 100, 8, 8, fake, fake, fake, 2, null, null, null, null, 8, fake, 1 << 20, null) == ARG
     assert bw(fake, 100, 8, 8, fake, fake, fake, 2, fake, null, null, fake, 8, fake, 256,
               null) == lib.PCA_ERR_WORKSPACE
+
+
+def test_batched_arguments_rejected_on_host(lib):
+    so = lib.library()
+    ARG = lib.PCA_ERR_ARG
+    null = ctypes.c_void_p(0)
+    fake = 4096
+    arr = (lib.PCACube * 2)()
+    arr[0] = lib.PCACube(fake, 1000, 64, 64, 5, fake, fake, fake, fake, 0)
+    arr[1] = lib.PCACube(fake, 5000, 37, 37, 3, fake, fake, fake, fake, 0)
+    cubes = ctypes.cast(ctypes.pointer(arr), ctypes.c_void_p)
+    dev = ctypes.c_void_p(fake)
+    ws = ctypes.c_void_p(fake)
+    need = lib.pca_batched_workspace_size(ctypes.pointer(arr), 2, 0, 30)
+    assert need > 0
+    ok = lambda *a: so.pca_batched(*a)
+    # No device copy of the descriptors, empty batch, bad mode.
+    assert ok(cubes, null, 2, 0, 0, 1e-6, 30, 1, null, ws, need, null) == ARG
+    assert ok(cubes, dev, 0, 0, 0, 1e-6, 30, 1, null, ws, need, null) == ARG
+    assert ok(cubes, dev, 2, 0, 9, 1e-6, 30, 1, null, ws, need, null) == ARG
+    # Workspace too small.
+    assert ok(cubes, dev, 2, 0, 0, 1e-6, 30, 1, null, ws, need - 1, null) == lib.PCA_ERR_WORKSPACE
+    # A cube with k > bands.
+    arr[1].k = 40
+    assert ok(cubes, dev, 2, 0, 0, 1e-6, 30, 1, null, ws, need, null) == ARG
+    arr[1].k = 3
+    # Tuning: chunk not a multiple of 32.
+    t = lib.PCABatchTuning(100, 4)
+    assert so.pca_batched(cubes, dev, 2, 0, 0, 1e-6, 30, 1, ctypes.cast(ctypes.pointer(t), ctypes.c_void_p), ws,
+                          need, null) == ARG
