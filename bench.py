@@ -15,7 +15,7 @@ fastest form whose eigenvalue error against the FP64 oracle is <= 1e-5
 kernels run on, the roofline of the dominant kernel, and the FP64 oracle timed
 on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube224|batch64]
 """
 
 from __future__ import annotations
@@ -141,6 +141,45 @@ def measured_traffic(kernel):
     return None if rec is None else rec.get("bytes_per_launch")
 
 
+def bench_batch(P, synth, torch, args):
+    """The batched form: 64 cubes with square sides 64..512 and 64..256 bands,
+    k = 5, through one pca_batched call captured in a HIP graph."""
+    log("generating the 64-cube batch ...")
+    cubes = synth.make_batch(64, 4000)
+    Yd = [torch.from_numpy(Y).cuda() for Y in cubes]
+    del cubes
+    mode = args.modes.split(",")[0] if args.modes != "f32,bf16x3,bf16x4" else "bf16x3"
+    b = P.BatchedPCA(Yd, 5, mode)
+    tuning = None
+    if args.autotune:
+        from paper_2403_18321_amd import autotune
+        tuning, _ = autotune.tune(b)
+    g = b.capture()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    pb = b.pixel_bands()
+    conv = sum(P.read_info(i)["converged"] for i in b.info)
+    out = dict(metric=METRIC, value=round(pb / (ms * 1e-3) / 1e6, 1), unit="Mpixel·band/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="bf16" if mode.startswith("bf16") else "f32",
+               data="synthetic",
+               config=dict(workload="64 cubes, square sides 64..512 px, 64..256 bands, k=5 (one pca_batched call, "
+                                    "graph replay)", pixel_bands=pb, cov_mode=mode, tuning=tuning,
+                           converged=f"{conv}/{len(b.info)}"))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +188,9 @@ def main(argv=None):
     ap.add_argument("--modes", default="f32,bf16x3,bf16x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--workload", choices=("cube224", "batch64"), default="cube224",
+                    help="cube224: the 224-band 1024x1024 cube (the reported line); batch64: the 64-cube batch")
+    ap.add_argument("--autotune", action="store_true", help="batch64: tune the tile shapes first")
     ap.add_argument("--copy-check", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration, copy ceiling)")
     args = ap.parse_args(argv)
@@ -168,6 +210,8 @@ def main(argv=None):
     import synth
 
     P.library()  # fail loudly if the HIP library is missing
+    if args.workload == "batch64":
+        return bench_batch(P, synth, torch, args)
     log("generating the 224-band cube ...")
     d = synth.make_config("c3")
     k = d["k"]
