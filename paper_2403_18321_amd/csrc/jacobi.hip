@@ -24,7 +24,7 @@
 // computes its rotation on the spot. The diagonal is float64 in a separate
 // double-buffered array, as are the rotations (tan, cos).
 //
-// jacobi_kernel (one workgroup of 512 threads, one CU). A step:
+// jacobi_kernel (one workgroup of 1024 threads, one CU). A step:
 //   a. every thread rotates its 2x2 blocks: rows by R_k^T, columns by R_l --
 //      the row and column updates of C_k = P^T C P, equation (8), for all
 //      pairs of the step at once;
@@ -53,12 +53,12 @@ namespace pca {
 
 namespace {
 
-constexpr int kJThreads = 512;
+constexpr int kJThreads = 1024;
 constexpr int kMaxP = 128;
 constexpr int kMaxRowBlocks = 9088;   // padded block rows for 128 pairs (see row_start)
 constexpr int kBlockPad = 32;         // tail that segment reads may run into
 constexpr int kCsPad = 32;
-constexpr int kLoadPerThread = 64;    // loads in flight per pass
+constexpr int kLoadPerThread = 16;    // loads in flight per pass
 constexpr double kFloorRel2 = 3.552713678800501e-15;   // (2^-24)^2
 
 struct Slots {
@@ -677,7 +677,7 @@ __global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const doub
 }
 
 // ---- batched form ------------------------------------------------------------
-constexpr int kBatchL = 19;   // segment length that fits every band count
+constexpr int kBatchL = 9;    // segment length that fits every band count (1024 threads)
 
 __device__ inline const BatchCube *jbatch_table(const char *ws)
 {
@@ -746,20 +746,16 @@ hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int 
     const int n = plan.me;
     const int P = plan.npairs;
     // Shortest segment length (odd, so that the lanes of a wave hit distinct
-    // LDS banks) that gives every segment its own thread.
+    // LDS banks) that gives every segment its own thread; 9 suffices for 128
+    // pairs with 1024 threads.
     int L = 1;
-    while (L < 19 && jac_segments(P, L) > kJThreads) L += 2;
+    while (L < kBatchL && jac_segments(P, L) > kJThreads) L += 2;
     switch (L) {
     case 1: launch_jac<1>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
     case 3: launch_jac<3>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
     case 5: launch_jac<5>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
     case 7: launch_jac<7>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    case 9: launch_jac<9>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    case 11: launch_jac<11>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    case 13: launch_jac<13>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    case 15: launch_jac<15>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    case 17: launch_jac<17>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    default: launch_jac<19>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    default: launch_jac<kBatchL>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
     }
     const int rows = replay_rows(n);
     const unsigned nwg = (unsigned)((n + rows - 1) / rows);
