@@ -31,4 +31,4 @@ from ._lib import (  # noqa: F401
 )
 from ._lib import PCABatchTuning, PCACube, pca_batched, pca_batched_workspace_size  # noqa: F401
 from .batched import BatchedPCA  # noqa: F401
-from .api import DEFAULT_MAX_SWEEPS, DEFAULT_TOL, PCAFunction, PCAPipeline, PCAResult, pca_autograd, run  # noqa: F401
+from .api import DEFAULT_MAX_SWEEPS, DEFAULT_TOL, PCAFunction, PCAPipeline, PCAResult, PCAStream, pca_autograd, run  # noqa: F401

@@ -68,6 +68,62 @@ class PCAPipeline:
         return PCAResult(self.mean, self.C, self.eigvals, self.V, self.Q, self.info)
 
 
+class PCAStream:
+    """A stream of cubes of one shape with several in flight at once.
+
+    Cube i runs on HIP stream i mod depth with its own buffers and workspaces,
+    so the single-CU Jacobi of one cube overlaps the all-CU streaming passes
+    (covariance, projection) of the others; every cube still goes through
+    the whole pipeline. With `chain` the covariance pass of cube i starts
+    only after that of cube i-1 has finished (an event between the streams),
+    which keeps the streams out of phase: their HBM-bound passes take turns
+    instead of all running at once while every Jacobi waits. submit() only
+    enqueues: the result of a submitted cube is valid once its event has
+    completed and stays valid until the same slot is reused `depth`
+    submissions later. The streams keep the default priority."""
+
+    def __init__(self, n_pixels: int, n_bands: int, k: int, mode: str = "f32", depth: int = 4,
+                 tol: float = DEFAULT_TOL, max_sweeps: int = DEFAULT_MAX_SWEEPS,
+                 fp64_angles: bool = True, device="cuda", chain: bool = True):
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
+        self.depth = int(depth)
+        self.chain = bool(chain)
+        self.pipes = [PCAPipeline(n_pixels, n_bands, k, mode, tol, max_sweeps, fp64_angles, device)
+                      for _ in range(self.depth)]
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(self.depth)]
+        self.events = [torch.cuda.Event() for _ in range(self.depth)]
+        self.cov_done = [torch.cuda.Event() for _ in range(self.depth)]
+        self.count = 0
+
+    def submit(self, Y):
+        """Enqueue the PCA of cube Y (after the work already queued on the
+        caller's current stream); returns (PCAResult, completion event)."""
+        s = self.count % self.depth
+        st = self.streams[s]
+        pipe = self.pipes[s]
+        if tuple(Y.shape) != (pipe.n, pipe.m):
+            raise ValueError(f"cube shape {tuple(Y.shape)} != ({pipe.n}, {pipe.m})")
+        st.wait_stream(torch.cuda.current_stream())
+        if self.chain and self.count > 0:
+            st.wait_event(self.cov_done[(self.count - 1) % self.depth])
+        Y.record_stream(st)
+        with torch.cuda.stream(st):
+            pipe.covariance(Y)
+            self.cov_done[s].record(st)
+            pipe.eigh()
+            pipe.project(Y)
+            self.events[s].record(st)
+        self.count += 1
+        return PCAResult(pipe.mean, pipe.C, pipe.eigvals, pipe.V, pipe.Q, pipe.info), self.events[s]
+
+    def join(self):
+        """Make the caller's current stream wait for every submitted cube."""
+        cur = torch.cuda.current_stream()
+        for st in self.streams:
+            cur.wait_stream(st)
+
+
 def run(Y: torch.Tensor, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
         max_sweeps: int = DEFAULT_MAX_SWEEPS, fp64_angles: bool = True) -> PCAResult:
     """PCA of one device cube Y [pixels, bands] (float32 or uint16)."""
