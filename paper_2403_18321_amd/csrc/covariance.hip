@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kThreads = 256;   // 4 waves; wave w loads pixel group w of a stage
 constexpr int KT = kCovTile;    // 32 pixels per stage = 4 groups of 8
-constexpr int kSlots = 9;       // accumulator blocks per wave (36 blocks / 4 waves)
+constexpr int kMaxSlots = 9;    // accumulator blocks per wave at 8 blocks per side (36 / 4 waves)
 constexpr int kFlush = 8;       // stages per first-level MFMA accumulation (float32 mode)
 constexpr int kBfPitch = KT + 8;  // bf16 per band row in LDS (80 bytes)
 
@@ -36,8 +36,23 @@ enum { MODE_F32 = 0, MODE_BF16X3 = 1, MODE_BF16X4 = 2 };
 // half-waves of an MFMA operand read fall on disjoint LDS banks.
 __host__ __device__ constexpr int f32_pitch(int mpad) { return (mpad % 64 == 0) ? mpad + 32 : mpad; }
 
-// Static id of the upper-triangle block (bi, bj), bi <= bj < 8.
-__host__ __device__ constexpr int static_block(int bi, int bj) { return bi * 8 - bi * (bi - 1) / 2 + (bj - bi); }
+// Work order of the upper-triangle 32x32 blocks: block (bi, bj), bi <= bj,
+// has id bj (bj + 1) / 2 + bi (column by column), so a matrix of nb blocks per
+// side uses exactly the ids below nb (nb + 1) / 2, whatever nb is. Wave w
+// owns ids w, w + 4, w + 8, ...; its slot e holds id 4 e + w.
+__device__ inline void block_of_id(int id, int &bi, int &bj)
+{
+    int j = 0;
+    while ((j + 1) * (j + 2) / 2 <= id) ++j;
+    bj = j;
+    bi = id - j * (j + 1) / 2;
+}
+// Accumulator slots per wave for nb blocks per side (a kernel variant each).
+__host__ __device__ inline int cov_slots(int nb)
+{
+    const int per_wave = (nb * (nb + 1) / 2 + 3) / 4;
+    return per_wave <= 3 ? 3 : (per_wave <= 6 ? 6 : (per_wave <= 7 ? 7 : kMaxSlots));
+}
 // Compact id for nb blocks per side (the layout of the partial results).
 __device__ inline int compact_block(int bi, int bj, int nb) { return bi * nb - bi * (bi - 1) / 2 + (bj - bi); }
 
@@ -49,7 +64,7 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 
 // One chunk c of one cube (the body of the single-cube and the batched
 // launches).
-template <typename T, int VEC, int MODE>
+template <typename T, int VEC, int MODE, int S>
 __device__ __forceinline__ void cov_partial_body(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
     int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
@@ -84,10 +99,10 @@ __device__ __forceinline__ void cov_partial_body(
     // a split-bfloat16 MFMA already sums 16 pixels per instruction, so one
     // level keeps its chains as short.
     constexpr bool kTwoLevel = MODE == MODE_F32;
-    constexpr int kSlots2 = kTwoLevel ? kSlots : 1;
-    f32x16 acc[kSlots], acc2[kSlots2];
+    constexpr int kSlots2 = kTwoLevel ? S : 1;
+    f32x16 acc[S], acc2[kSlots2];
 #pragma unroll
-    for (int e = 0; e < kSlots; ++e) {
+    for (int e = 0; e < S; ++e) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[e][r] = 0.f;
     }
@@ -107,6 +122,24 @@ __device__ __forceinline__ void cov_partial_body(
     bool bok[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) bok[s] = slot_band<VEC>(lane, s) < m;
+
+    // LDS operand offsets of this wave's blocks (slot e: id 4 e + wave). A slot
+    // past the last block multiplies block (0, 0) again and is never stored,
+    // so the product loop has no branches.
+    const int nbl = nb * (nb + 1) / 2;
+    int offI[S], offJ[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        int bi = 0, bj = 0;
+        if (4 * e + wave < nbl) block_of_id(4 * e + wave, bi, bj);
+        if constexpr (MODE == MODE_F32) {
+            offI[e] = 32 * bi + (lane & 31);
+            offJ[e] = 32 * bj + (lane & 31);
+        } else {
+            offI[e] = (32 * bi + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
+            offJ[e] = (32 * bj + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
+        }
+    }
 
     auto stage = [&](Group<T, VEC> &v, int64_t st) {
         const int64_t g0 = pbeg + st * KT + 8 * wave;  // first pixel of this wave's group
@@ -166,51 +199,27 @@ __device__ __forceinline__ void cov_partial_body(
         if constexpr (MODE == MODE_F32) {
 #pragma unroll 2
             for (int kk = 0; kk < KT / 2; ++kk) {
-                float op[8];
-                const int row = 2 * kk + (lane >> 5);
+                const float *tr = tileF + (2 * kk + (lane >> 5)) * pf;
 #pragma unroll
-                for (int bb = 0; bb < 8; ++bb)
-                    op[bb] = (bb < nb) ? tileF[row * pf + 32 * bb + (lane & 31)] : 0.f;
-#pragma unroll
-                for (int bi = 0; bi < 8; ++bi) {
-#pragma unroll
-                    for (int bj = bi; bj < 8; ++bj) {
-                        const int E = static_block(bi, bj);
-                        if ((E & 3) != wave || bj >= nb) continue;
-                        acc[E >> 2] = __builtin_amdgcn_mfma_f32_32x32x2f32(op[bi], op[bj], acc[E >> 2], 0, 0, 0);
-                    }
-                }
+                for (int e = 0; e < S; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(tr[offI[e]], tr[offJ[e]], acc[e], 0, 0, 0);
             }
         } else {
 #pragma unroll
             for (int kk = 0; kk < KT / 16; ++kk) {
-                bf16x8 oh[8], ol[8];
-                const int col = 16 * kk + 8 * (lane >> 5);
 #pragma unroll
-                for (int bb = 0; bb < 8; ++bb) {
-                    if (bb < nb) {
-                        const int row = 32 * bb + (lane & 31);
-                        oh[bb] = *reinterpret_cast<const bf16x8 *>(&hiT[row * kBfPitch + col]);
-                        ol[bb] = *reinterpret_cast<const bf16x8 *>(&loT[row * kBfPitch + col]);
-                    } else {
-                        oh[bb] = bf16x8{};
-                        ol[bb] = bf16x8{};
-                    }
-                }
-#pragma unroll
-                for (int bi = 0; bi < 8; ++bi) {
-#pragma unroll
-                    for (int bj = bi; bj < 8; ++bj) {
-                        const int E = static_block(bi, bj);
-                        if ((E & 3) != wave || bj >= nb) continue;
-                        f32x16 a = acc[E >> 2];
-                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(oh[bi], oh[bj], a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(oh[bi], ol[bj], a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ol[bi], oh[bj], a, 0, 0, 0);
-                        if constexpr (MODE == MODE_BF16X4)
-                            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ol[bi], ol[bj], a, 0, 0, 0);
-                        acc[E >> 2] = a;
-                    }
+                for (int e = 0; e < S; ++e) {
+                    const bf16x8 hi_i = *reinterpret_cast<const bf16x8 *>(&hiT[offI[e] + 16 * kk]);
+                    const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&loT[offI[e] + 16 * kk]);
+                    const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hiT[offJ[e] + 16 * kk]);
+                    const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&loT[offJ[e] + 16 * kk]);
+                    f32x16 a = acc[e];
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
+                    if constexpr (MODE == MODE_BF16X4)
+                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
+                    acc[e] = a;
                 }
             }
         }
@@ -219,7 +228,7 @@ __device__ __forceinline__ void cov_partial_body(
         if constexpr (kTwoLevel) {
             if ((st + 1) % kFlush == 0) {
 #pragma unroll
-                for (int e = 0; e < kSlots; ++e) {
+                for (int e = 0; e < S; ++e) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) { acc2[e][r] += acc[e][r]; acc[e][r] = 0.f; }
                 }
@@ -232,16 +241,16 @@ __device__ __forceinline__ void cov_partial_body(
         if (PREF == 2 && st + 1 < nst) stage(gb, st + 1);
     }
 
-    // Partial second moment of this chunk: [chunk][block][reg][lane].
+    // Partial second moment of this chunk: [chunk][block][reg][lane], blocks
+    // in the row-major compact order the finalisation reads.
 #pragma unroll
-    for (int bi = 0; bi < 8; ++bi) {
-#pragma unroll
-        for (int bj = bi; bj < 8; ++bj) {
-            const int E = static_block(bi, bj);
-            if ((E & 3) != wave || bj >= nb) continue;
+    for (int e = 0; e < S; ++e) {
+        if (4 * e + wave < nbl) {
+            int bi, bj;
+            block_of_id(4 * e + wave, bi, bj);
             float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) dst[r * 64] = kTwoLevel ? acc2[(E >> 2) % kSlots2][r] + acc[E >> 2][r] : acc[E >> 2][r];
+            for (int r = 0; r < 16; ++r) dst[r * 64] = kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r];
         }
     }
 
@@ -263,13 +272,280 @@ __device__ __forceinline__ void cov_partial_body(
     }
 }
 
-template <typename T, int VEC, int MODE>
+template <typename T, int VEC, int MODE, int S>
 __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
     int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
 {
-    cov_partial_body<T, VEC, MODE>(Y, n, m, ld, centered, chunk, nb, nblk, mpad, partS, partSum, partShift,
-                                   (int64_t)blockIdx.x);
+    cov_partial_body<T, VEC, MODE, S>(Y, n, m, ld, centered, chunk, nb, nblk, mpad, partS, partSum, partShift,
+                                      (int64_t)blockIdx.x);
+}
+
+// ---- float32 cubes with 16-byte aligned rows: pixel rows copied into LDS --
+//
+// The same chunk algorithm, organised for this case:
+//  * the raw pixel rows go from HBM straight into LDS through the load unit
+//    (global_load_lds_dwordx4: lane l's 16 bytes land at base + 16 l),
+//    kRing - 1 stages ahead of use, so no registers are tied up by loads in
+//    flight. The ring slots are three separate LDS arrays used in a fixed
+//    rotation, which lets the compiler see that reading one slot does not
+//    wait on the copies into the others; the copy waits (vmcnt) and the
+//    barriers are explicit;
+//  * 8 waves of modest register use, two per SIMD, so that one wave's
+//    centring and splitting overlaps another's matrix products;
+//  * the chunk shift is always the chunk's first pixel; rows past the chunk
+//    end, and lanes past the last band, copy that pixel's values, so they
+//    centre to exact zeros without masks.
+constexpr int kRing = 3;
+constexpr int kDmaWaves = 8;
+constexpr int kDmaThreads = 64 * kDmaWaves;
+constexpr int kDmaPix = KT / kDmaWaves;   // pixels per wave per stage (copies per wave per stage)
+
+// Accumulator slots per wave (blocks id = kDmaWaves e + wave) for nb blocks
+// per side.
+__host__ __device__ inline int dma_slots(int nb)
+{
+    const int per_wave = (nb * (nb + 1) / 2 + kDmaWaves - 1) / kDmaWaves;
+    return per_wave <= 2 ? 2 : per_wave;   // 2, 3, 4 or 5
+}
+
+// s_waitcnt immediates (gfx9 layout: vmcnt[3:0] and [15:14], expcnt[6:4],
+// lgkmcnt[11:8]; all-ones fields do not wait).
+constexpr int waitcnt_vm(int n) { return (n & 0xF) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8); }
+constexpr int kWaitLgkm0 = 0xF | (0x3 << 14) | (0x7 << 4);
+
+// Workgroup barrier for LDS traffic only: this wave's LDS reads and writes
+// complete, then s_barrier (a __syncthreads would also wait for the copies
+// in flight). The empty asm statements keep the compiler from moving memory
+// operations across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+
+template <int MODE, int S>
+__global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
+    const float *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+{
+    // Staged pixel rows: 256 floats (288 for the float32 products, whose two
+    // half-waves read rows one apart).
+    constexpr int pitch = MODE == MODE_F32 ? 288 : 256;
+    constexpr int kRawFloats = KT * pitch;
+    constexpr int kHalf = 256 * kBfPitch;   // bf16 per tile (hi, then lo)
+    __shared__ __attribute__((aligned(16))) float raw0[kRawFloats];
+    __shared__ __attribute__((aligned(16))) float raw1[kRawFloats];
+    __shared__ __attribute__((aligned(16))) float raw2[kRawFloats];
+    __shared__ __attribute__((aligned(16))) __bf16 hl[MODE == MODE_F32 ? 8 : 2 * kHalf];
+    __shared__ float shv[256];
+    static_assert(kRawFloats * sizeof(float) >= kDmaWaves * 256 * sizeof(double), "band-sum scratch");
+    double(*red)[256] = reinterpret_cast<double(*)[256]>(raw0);   // used after the ring is drained
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t c = blockIdx.x;
+    const int64_t pbeg = c * chunk;
+    const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
+    const int64_t nst = (pend - pbeg + KT - 1) / KT;
+    const int loff = 4 * lane < m ? 4 * lane : 0;   // m % 4 == 0 on this path
+    const float *row0 = Y + pbeg * ld;
+
+    // Workgroups walk their chunks from different starting stages (evenly
+    // spread over the chunk, wrapping around): chunks are equal power-of-two
+    // multiples of bytes apart, and in lockstep every workgroup would hit
+    // the same HBM channel at the same moment.
+    const int64_t rot = (c * nst) / gridDim.x;
+    // Copies of the stage at position t of this walk (pixels pbeg + 32 t'
+    // with t' = (t + rot) mod nst; positions past the end copy the first
+    // pixel) into ring slot R.
+    auto issue = [&](float *R, int64_t t) {
+        const int64_t tt = t < nst ? (t + rot < nst ? t + rot : t + rot - nst) : nst;
+#pragma unroll
+        for (int i = 0; i < kDmaPix; ++i) {
+            const int64_t p = pbeg + tt * KT + kDmaPix * wave + i;
+            const float *rowp = (p < pend && loff == 4 * lane) ? Y + p * ld : row0;
+            __builtin_amdgcn_global_load_lds(rowp + loff, R + (kDmaPix * wave + i) * pitch, 16, 0, 0);
+        }
+    };
+
+    const f32x4 shift = *reinterpret_cast<const f32x4 *>(row0 + loff);
+    if (wave == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) shv[4 * lane + s] = shift[s];
+    }
+    asm volatile("" ::: "memory");   // the shift load and store stay ahead of the copies
+    issue(raw0, 0);
+    issue(raw1, 1);
+
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    constexpr bool kTwoLevel = MODE == MODE_F32;
+    constexpr int kSlots2 = kTwoLevel ? S : 1;
+    f32x16 acc[S], acc2[kSlots2];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[e][r] = 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < kSlots2; ++e) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc2[e][r] = 0.f;
+    }
+
+    // Operand offsets of this wave's blocks (slot e: id kDmaWaves e + wave; a
+    // slot past the last block repeats block (0, 0) and is never stored).
+    const int nbl = nb * (nb + 1) / 2;
+    int offI[S], offJ[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        int bi = 0, bj = 0;
+        if (kDmaWaves * e + wave < nbl) block_of_id(kDmaWaves * e + wave, bi, bj);
+        if constexpr (MODE == MODE_F32) {
+            offI[e] = 32 * bi + (lane & 31);
+            offJ[e] = 32 * bj + (lane & 31);
+        } else {
+            offI[e] = (32 * bi + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
+            offJ[e] = (32 * bj + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
+        }
+    }
+    lds_barrier();   // shv visible
+    // Centring works on bands lane + 64 s (consecutive lanes, consecutive
+    // band rows of the tiles, so their tile stores spread over the banks).
+    float shb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) shb[s] = shv[lane + 64 * s];
+    float shI[S], shJ[S];
+    if constexpr (MODE == MODE_F32) {
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            shI[e] = shv[offI[e]];
+            shJ[e] = shv[offJ[e]];
+        }
+    }
+
+    // This wave's pixels of a landed stage, centred: band sums (float32 over
+    // the stage's 4 pixels, then float64) and, for the split forms, the hi /
+    // lo tiles in LDS, band-major.
+    auto centre = [&](const float *R) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int b = lane + 64 * s;
+            if (b >= mpad) continue;
+            float x[kDmaPix];
+#pragma unroll
+            for (int i = 0; i < kDmaPix; ++i) x[i] = R[(kDmaPix * wave + i) * pitch + b] - shb[s];
+            sums[s] += (double)((x[0] + x[1]) + (x[2] + x[3]));
+            if constexpr (MODE != MODE_F32) {
+                bf16x4 h, l;
+#pragma unroll
+                for (int q = 0; q < kDmaPix / 2; ++q) {
+                    const f32x2 v = {x[2 * q], x[2 * q + 1]};
+                    const bf16x2 hh = __builtin_convertvector(v, bf16x2);
+                    const f32x2 r = v - __builtin_convertvector(hh, f32x2);
+                    const bf16x2 ll = __builtin_convertvector(r, bf16x2);
+                    h[2 * q] = hh[0];
+                    h[2 * q + 1] = hh[1];
+                    l[2 * q] = ll[0];
+                    l[2 * q + 1] = ll[1];
+                }
+                *reinterpret_cast<bf16x4 *>(&hl[b * kBfPitch + kDmaPix * wave]) = h;
+                *reinterpret_cast<bf16x4 *>(&hl[kHalf + b * kBfPitch + kDmaPix * wave]) = l;
+            }
+        }
+    };
+
+    auto products = [&](const float *R) {
+        if constexpr (MODE == MODE_F32) {
+#pragma unroll 2
+            for (int kk = 0; kk < KT / 2; ++kk) {
+                const float *tr = R + (2 * kk + (lane >> 5)) * pitch;
+#pragma unroll
+                for (int e = 0; e < S; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(tr[offI[e]] - shI[e], tr[offJ[e]] - shJ[e], acc[e],
+                                                                 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KT / 16; ++kk) {
+#pragma unroll
+                for (int e = 0; e < S; ++e) {
+                    const bf16x8 hi_i = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
+                    const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
+                    const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
+                    const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
+                    f32x16 a = acc[e];
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
+                    if constexpr (MODE == MODE_BF16X4)
+                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
+                    acc[e] = a;
+                }
+            }
+        }
+    };
+
+    // One stage in ring slot `cur`; the copies for two stages ahead go into
+    // `nxt` (the slot of the previous stage, which every wave has finished
+    // reading once past the first barrier). The stage count is rounded up to
+    // a multiple of the ring: stages past the chunk end are copies of its
+    // first pixel, which centre to exact zeros and add nothing, so every step
+    // is the same straight-line code with one copy wait.
+    auto step = [&](float *cur, float *nxt, int64_t st) {
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(kDmaPix));
+        lds_barrier();
+        issue(nxt, st + 2);
+        centre(cur);
+        if constexpr (MODE != MODE_F32) lds_barrier();
+        products(cur);
+        if constexpr (kTwoLevel) {
+            if ((st + 1) % kFlush == 0) {
+#pragma unroll
+                for (int e = 0; e < S; ++e) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) { acc2[e][r] += acc[e][r]; acc[e][r] = 0.f; }
+                }
+            }
+        }
+    };
+
+    for (int64_t st = 0; st < nst; st += kRing) {
+        step(raw0, raw2, st);
+        step(raw1, raw0, st + 1);
+        step(raw2, raw1, st + 2);
+    }
+    // The stages copied ahead past the end must land before the workgroup's
+    // LDS is reused (the band sums below, or another workgroup).
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    __syncthreads();
+
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        if (kDmaWaves * e + wave < nbl) {
+            int bi, bj;
+            block_of_id(kDmaWaves * e + wave, bi, bj);
+            float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) dst[r * 64] = kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) red[wave][lane + 64 * s] = sums[s];
+    __syncthreads();
+    for (int b = tid; b < mpad; b += kDmaThreads) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kDmaWaves; ++w) t += red[w][b];
+        partSum[c * mpad + b] = t;
+        partShift[c * mpad + b] = shv[b];
+    }
 }
 
 // Pass 2a: grid (block, chunk group). Every workgroup forms the band means of
@@ -327,7 +603,7 @@ __device__ __forceinline__ void cov_finalize_part_body(
             const double sm = partSum[w * mpad + bb];
             const float sh = partShift[w * mpad + bb];
             smv[cc][q] = ok ? sm : 0.0;
-            shv[cc][q] = (ok && !centered) ? sh : 0.f;
+            shv[cc][q] = ok ? sh : 0.f;   // any shift is exact algebra; centred cubes may store one too
         }
         float sv[kBatch];
 #pragma unroll
@@ -428,8 +704,9 @@ __global__ __launch_bounds__(kThreads) void cov_partial_batched_kernel(char *ws,
         const int64_t item = item_sh;
         if (item >= total) break;
         const BatchCube &cb = t[batch_find<&BatchCube::w_cov>(t, nc, item)];
-        cov_partial_body<T, 1, MODE>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, 0, cb.cov.chunk, cb.cov.nb,
-                                     cb.cov.nblk, cb.cov.mpad, cb.partS, cb.partSum, cb.partShift, item - cb.w_cov);
+        cov_partial_body<T, 1, MODE, kMaxSlots>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, 0, cb.cov.chunk,
+                                                cb.cov.nb, cb.cov.nblk, cb.cov.mpad, cb.partS, cb.partSum,
+                                                cb.partShift, item - cb.w_cov);
     }
 }
 
@@ -453,26 +730,80 @@ __global__ __launch_bounds__(1024) void cov_finalize_sum_batched_kernel(const ch
                           (int)(item - cb.w_fin2));
 }
 
+template <typename T, int VEC, int MODE>
+hipError_t launch_partial_m(const T *Y, int64_t n, int m, int64_t ld, int centered, const CovPlan &p,
+                            float *partS, double *partSum, float *partShift, hipStream_t st)
+{
+    dim3 grid((unsigned)p.nchunks), block(kThreads);
+    switch (cov_slots(p.nb)) {
+    case 3:
+        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE, 3>), grid, block, 0, st, Y, n, m, ld, centered, p.chunk,
+                           p.nb, p.nblk, p.mpad, partS, partSum, partShift);
+        break;
+    case 6:
+        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE, 6>), grid, block, 0, st, Y, n, m, ld, centered, p.chunk,
+                           p.nb, p.nblk, p.mpad, partS, partSum, partShift);
+        break;
+    case 7:
+        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE, 7>), grid, block, 0, st, Y, n, m, ld, centered, p.chunk,
+                           p.nb, p.nblk, p.mpad, partS, partSum, partShift);
+        break;
+    default:
+        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE, kMaxSlots>), grid, block, 0, st, Y, n, m, ld, centered,
+                           p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_dma_m(const float *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
+                        double *partSum, float *partShift, hipStream_t st)
+{
+    dim3 grid((unsigned)p.nchunks), block(kDmaThreads);
+    switch (dma_slots(p.nb)) {
+    case 2:
+        hipLaunchKernelGGL((cov_partial_dma_kernel<MODE, 2>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
+                           p.mpad, partS, partSum, partShift);
+        break;
+    case 3:
+        hipLaunchKernelGGL((cov_partial_dma_kernel<MODE, 3>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
+                           p.mpad, partS, partSum, partShift);
+        break;
+    case 4:
+        hipLaunchKernelGGL((cov_partial_dma_kernel<MODE, 4>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
+                           p.mpad, partS, partSum, partShift);
+        break;
+    default:
+        hipLaunchKernelGGL((cov_partial_dma_kernel<MODE, 5>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
+                           p.mpad, partS, partSum, partShift);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_partial_dma(const float *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p,
+                              float *partS, double *partSum, float *partShift, hipStream_t st)
+{
+    switch (mode) {
+    case MODE_F32: return launch_dma_m<MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    case MODE_BF16X3: return launch_dma_m<MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    default: return launch_dma_m<MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    }
+}
+
 template <typename T, int VEC>
 hipError_t launch_partial_t(const T *Y, int64_t n, int m, int64_t ld, int centered, int mode,
                             const CovPlan &p, float *partS, double *partSum, float *partShift, hipStream_t st)
 {
-    dim3 grid((unsigned)p.nchunks), block(kThreads);
     switch (mode) {
     case MODE_F32:
-        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_F32>), grid, block, 0, st, Y, n, m, ld,
-                           centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift);
-        break;
+        return launch_partial_m<T, VEC, MODE_F32>(Y, n, m, ld, centered, p, partS, partSum, partShift, st);
     case MODE_BF16X3:
-        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_BF16X3>), grid, block, 0, st, Y, n, m,
-                           ld, centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift);
-        break;
+        return launch_partial_m<T, VEC, MODE_BF16X3>(Y, n, m, ld, centered, p, partS, partSum, partShift, st);
     default:
-        hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE_BF16X4>), grid, block, 0, st, Y, n, m,
-                           ld, centered, p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift);
-        break;
+        return launch_partial_m<T, VEC, MODE_BF16X4>(Y, n, m, ld, centered, p, partS, partSum, partShift, st);
     }
-    return hipGetLastError();
 }
 
 }  // namespace
@@ -502,6 +833,8 @@ hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t l
                               float *partShift, hipStream_t st)
 {
     const bool v4 = vec4_ok(Y, dt, m, ld);
+    if (dt == PCA_IN_F32 && v4) return launch_partial_dma(static_cast<const float *>(Y), n, m, ld, mode, plan, partS,
+                                                          partSum, partShift, st);
     if (dt == PCA_IN_F32) {
         const float *y = static_cast<const float *>(Y);
         return v4 ? launch_partial_t<float, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st)
