@@ -31,10 +31,11 @@ import sys
 import time
 
 # The stream measurement keeps several cubes in flight, one HIP stream each;
-# HIP maps streams onto this many hardware queues per process (its default
-# is 4, which would make some streams share a queue and serialise). It must
-# be set before the runtime starts, so here, before torch is imported.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# HIP maps streams onto this many hardware queues per process (4 by default,
+# which makes some of the streams share a queue and serialise). It must be
+# set before the runtime starts, so here, before torch is imported; it only
+# concerns this process, and the one-stream timings do not depend on it.
+os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
