@@ -177,13 +177,14 @@ def measured_traffic(kernel):
 
 def bench_batch(P, synth, torch, args):
     """The batched form: 64 cubes with square sides 64..512 and 64..256 bands,
-    k = 5, through one pca_batched call captured in a HIP graph."""
+    k = 5, through pca_batched calls (one per lane: sub-batches by band count
+    on their own HIP streams) captured in one HIP graph."""
     log("generating the 64-cube batch ...")
     cubes = synth.make_batch(64, 4000)
     Yd = [torch.from_numpy(Y).cuda() for Y in cubes]
     del cubes
     mode = args.modes.split(",")[0] if args.modes != "f32,bf16x3,bf16x4" else "bf16x3"
-    b = P.BatchedPCA(Yd, 5, mode)
+    b = P.BatchedPCA(Yd, 5, mode, lanes=args.lanes)
     tuning = None
     if args.autotune:
         from paper_2403_18321_amd import autotune
@@ -207,9 +208,9 @@ def bench_batch(P, synth, torch, args):
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="bf16" if mode.startswith("bf16") else "f32",
                data="synthetic",
-               config=dict(workload="64 cubes, square sides 64..512 px, 64..256 bands, k=5 (one pca_batched call, "
+               config=dict(workload="64 cubes, square sides 64..512 px, 64..256 bands, k=5 (pca_batched per lane, "
                                     "graph replay)", pixel_bands=pb, cov_mode=mode, tuning=tuning,
-                           converged=f"{conv}/{len(b.info)}"))
+                           lanes=[len(g) for g in b.groups], converged=f"{conv}/{len(b.info)}"))
     print(json.dumps(out), flush=True)
     return 0
 
@@ -225,6 +226,8 @@ def main(argv=None):
     ap.add_argument("--workload", choices=("cube224", "batch64"), default="cube224",
                     help="cube224: the 224-band 1024x1024 cube (the reported line); batch64: the 64-cube batch")
     ap.add_argument("--autotune", action="store_true", help="batch64: tune the tile shapes first")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="batch64: sub-batches by band count, one pca_batched call and HIP stream each")
     ap.add_argument("--stream-depth", type=int, default=6,
                     help="cube224: also time a stream of cubes with this many in flight (0: skip)")
     ap.add_argument("--copy-check", action="store_true",

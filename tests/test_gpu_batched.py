@@ -201,3 +201,25 @@ def test_batched_argument_errors(pca):
         pca.BatchedPCA(Yd, [1, 1000])          # k > bands
     with pytest.raises(pca.PCAError):
         pca.BatchedPCA(Yd, [1, 1], tuning=(100, 4))   # chunk not a multiple of 32
+
+
+def test_batched_lanes_bitwise(pca):
+    """Splitting the batch into lanes (sub-batches by band count, each on its
+    own stream) changes no cube's result: every cube's work items are the
+    same whatever else is in its sub-batch. Also under graph capture."""
+    cubes, ks = small_batch()
+    Yd = [dev(Y) for Y in cubes]
+    one = pca.BatchedPCA(Yd, ks, "bf16x3")
+    one.run()
+    ref = _snapshot(one)
+    three = pca.BatchedPCA(Yd, ks, "bf16x3", lanes=3)
+    assert len(three.groups) == 3 and sorted(i for g in three.groups for i in g) == list(range(len(cubes)))
+    three.run()
+    assert all(np.array_equal(a, c) for a, c in zip(ref, _snapshot(three)))
+    g = three.capture()
+    for rep in range(2):
+        for t in three.eigvals + three.V + three.Q + three.mean:
+            t.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert all(np.array_equal(a, c) for a, c in zip(ref, _snapshot(three))), rep
