@@ -46,10 +46,17 @@ typedef enum {
     PCA_ERR_HIP = 4           /* a HIP launch or attribute call failed */
 } pca_status;
 
-/* Element type of the cube. */
+/* Element type and layout of the cube. Band-interleaved by pixel (BIP):
+ * Y[p * ld_y + b], ld_y >= n_bands, a pixel's bands contiguous, as push-broom
+ * sensors deliver it. Band-sequential (BSQ): Y[b * ld_y + p], ld_y >=
+ * n_pixels, a band's pixels contiguous: the layout of the paper's GPU
+ * design (Section 4). BSQ is accepted by pca_center, pca_covariance and
+ * pca_project; pca_backward and pca_batched take BIP cubes. */
 typedef enum {
-    PCA_IN_F32 = 0,           /* float32 */
-    PCA_IN_U16 = 1            /* uint16 (e.g. raw radiance counts), read as exact integers */
+    PCA_IN_F32 = 0,           /* float32, BIP */
+    PCA_IN_U16 = 1,           /* uint16 (e.g. raw radiance counts), read as exact integers, BIP */
+    PCA_IN_F32_BSQ = 2,       /* float32, BSQ */
+    PCA_IN_U16_BSQ = 3        /* uint16, BSQ */
 } pca_in_dtype;
 
 /* Arithmetic of the covariance products (the sums are always combined in
@@ -118,9 +125,10 @@ pca_status pca_workspace_size(int op, int64_t n_pixels, int32_t n_bands, int32_t
 /*
  * Band-average removal (Algorithm 1, line 2; the per-band average of the
  * GPU design's Code 4.2.1 and its subtraction, Code 4.2.2).
- *   Y     [n_pixels][ld_y] cube of type dt.
+ *   Y     cube of type and layout dt ([n_pixels][ld_y] BIP, [n_bands][ld_y] BSQ).
  *   mean  [n_bands] float32 out: mu_b = (1/N) sum_p Y[p, b], summed in float64.
- *   X     [n_pixels][ld_x] float32 out: Y - 1 mu^T, or NULL to write only mean.
+ *   X     float32 out in the layout of Y ([n_pixels][ld_x] BIP, [n_bands][ld_x]
+ *         BSQ): Y - 1 mu^T, or NULL to write only mean.
  *   ws    workspace of pca_workspace_size(PCA_OP_CENTER, ...) bytes.
  */
 pca_status pca_center(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y,
@@ -134,7 +142,8 @@ pca_status pca_center(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, 
  * sum (y - s)(y - s)^T and sum (y - s) about its first pixel s on chip, and
  * the chunk results are combined in float64 in chunk order into the centred
  * second moment (exact algebra, no cancellation against a global mean).
- *   Y                  [n_pixels][ld_y] cube of type dt.
+ *   Y                  cube of type and layout dt ([n_pixels][ld_y] BIP,
+ *                      [n_bands][ld_y] BSQ).
  *   input_is_centered  1: Y already is X (C = Y^T Y / (N-1), mean not written);
  *                      0: centre on the fly.
  *   mean               [n_bands] float32 out (may be NULL).
@@ -173,6 +182,7 @@ pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t 
 /*
  * Projection onto the first k eigenvectors (Algorithm 1, lines 5-6):
  *   Q[p, i] = sum_b (Y[p, b] - mean[b]) V[b, i],  i < k.
+ *   Y     cube of type and layout dt ([n_pixels][ld_y] BIP, [n_bands][ld_y] BSQ).
  *   mean  [n_bands] float32, or NULL when Y is already centred.
  *   V     [n_bands][n_bands] float32, column i = eigenvector i.
  *   Q     [n_pixels][k] float32 out. 1 <= k <= n_bands.

@@ -12,6 +12,8 @@ from ._lib import (  # noqa: F401
     PCA_COV_F32,
     PCA_IN_F32,
     PCA_IN_U16,
+    PCA_IN_F32_BSQ,
+    PCA_IN_U16_BSQ,
     PCA_OP_CENTER,
     PCA_OP_COVARIANCE,
     PCA_OP_JACOBI,

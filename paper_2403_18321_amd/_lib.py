@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpca.so")
 
 PCA_OK, PCA_ERR_ARG, PCA_ERR_UNSUPPORTED, PCA_ERR_WORKSPACE, PCA_ERR_HIP = range(5)
-PCA_IN_F32, PCA_IN_U16 = 0, 1
+PCA_IN_F32, PCA_IN_U16, PCA_IN_F32_BSQ, PCA_IN_U16_BSQ = 0, 1, 2, 3
 PCA_COV_F32, PCA_COV_BF16X3, PCA_COV_BF16X4 = 0, 1, 2
 PCA_OP_CENTER, PCA_OP_COVARIANCE, PCA_OP_JACOBI, PCA_OP_PROJECT, PCA_OP_BACKWARD = range(5)
 
@@ -109,9 +109,14 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _cube(Y: torch.Tensor):
+def _cube(Y: torch.Tensor, layout: str = "bip"):
+    """(dt, n_pixels, n_bands, ld) of a device cube: [pixels, bands] with unit
+    band stride ("bip"), or [bands, pixels] with unit pixel stride ("bsq")."""
+    if layout not in ("bip", "bsq"):
+        raise ValueError(f"layout must be 'bip' or 'bsq', not {layout!r}")
     if Y.dim() != 2 or Y.stride(1) != 1:
-        raise ValueError("cube must be a 2-D [pixels, bands] tensor with unit band stride")
+        raise ValueError("cube must be a 2-D tensor with unit stride along its second axis "
+                         "([pixels, bands] for bip, [bands, pixels] for bsq)")
     if Y.dtype == torch.float32:
         dt = PCA_IN_F32
     elif Y.dtype == torch.uint16:
@@ -120,6 +125,8 @@ def _cube(Y: torch.Tensor):
         raise ValueError(f"unsupported cube dtype {Y.dtype}")
     if not Y.is_cuda:
         raise ValueError("cube must be a device tensor")
+    if layout == "bsq":
+        return dt + 2, Y.shape[1], Y.shape[0], Y.stride(0)
     return dt, Y.shape[0], Y.shape[1], Y.stride(0)
 
 
@@ -137,8 +144,8 @@ def workspace(nbytes: int, device=None) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
 
 
-def pca_center(Y, mean, X=None, ws=None):
-    dt, n, m, ld = _cube(Y)
+def pca_center(Y, mean, X=None, ws=None, layout: str = "bip"):
+    dt, n, m, ld = _cube(Y, layout)
     if ws is None:
         ws = workspace(pca_workspace_size(PCA_OP_CENTER, n, m), Y.device)
     ldx = X.stride(0) if X is not None else 0
@@ -146,8 +153,9 @@ def pca_center(Y, mean, X=None, ws=None):
                                            ws.numel(), _stream()))
 
 
-def pca_covariance(Y, C, mean=None, mode: int = PCA_COV_F32, input_is_centered: bool = False, ws=None):
-    dt, n, m, ld = _cube(Y)
+def pca_covariance(Y, C, mean=None, mode: int = PCA_COV_F32, input_is_centered: bool = False, ws=None,
+                   layout: str = "bip"):
+    dt, n, m, ld = _cube(Y, layout)
     if ws is None:
         ws = workspace(pca_workspace_size(PCA_OP_COVARIANCE, n, m, mode=mode), Y.device)
     _check("pca_covariance", _lib().pca_covariance(_ptr(Y), dt, n, m, ld, int(bool(input_is_centered)), _ptr(mean),
@@ -163,8 +171,8 @@ def pca_jacobi_eigh(C, eigvals, V, tol: float, max_sweeps: int, fp64_angles: boo
                                                      _stream()))
 
 
-def pca_project(Y, mean, V, k: int, Q):
-    dt, n, m, ld = _cube(Y)
+def pca_project(Y, mean, V, k: int, Q, layout: str = "bip"):
+    dt, n, m, ld = _cube(Y, layout)
     _check("pca_project", _lib().pca_project(_ptr(Y), dt, n, m, ld, _ptr(mean), _ptr(V), int(k), _ptr(Q),
                                              _stream()))
 

@@ -33,8 +33,11 @@ class PCAPipeline:
 
     def __init__(self, n_pixels: int, n_bands: int, k: int, mode: str = "f32",
                  tol: float = DEFAULT_TOL, max_sweeps: int = DEFAULT_MAX_SWEEPS,
-                 fp64_angles: bool = True, device="cuda"):
+                 fp64_angles: bool = True, device="cuda", layout: str = "bip"):
+        """layout: "bip" for [pixels, bands] cubes, "bsq" for [bands, pixels]
+        (band-sequential) cubes."""
         self.n, self.m, self.k = int(n_pixels), int(n_bands), int(k)
+        self.layout = layout
         self.mode = L.COV_MODES[mode] if isinstance(mode, str) else int(mode)
         self.tol, self.max_sweeps, self.fp64_angles = float(tol), int(max_sweeps), bool(fp64_angles)
         dev = torch.device(device)
@@ -50,18 +53,21 @@ class PCAPipeline:
                                                        max_sweeps=self.max_sweeps), dev)
 
     def covariance(self, Y):
-        L.pca_covariance(Y, self.C, self.mean, self.mode, False, self.ws_cov)
+        L.pca_covariance(Y, self.C, self.mean, self.mode, False, self.ws_cov, layout=self.layout)
 
     def eigh(self):
         L.pca_jacobi_eigh(self.C, self.eigvals, self.V, self.tol, self.max_sweeps, self.fp64_angles,
                           self.info, self.ws_jac)
 
     def project(self, Y):
-        L.pca_project(Y, self.mean, self.V, self.k, self.Q)
+        L.pca_project(Y, self.mean, self.V, self.k, self.Q, layout=self.layout)
+
+    def shape(self):
+        return (self.m, self.n) if self.layout == "bsq" else (self.n, self.m)
 
     def forward(self, Y) -> PCAResult:
-        if tuple(Y.shape) != (self.n, self.m):
-            raise ValueError(f"cube shape {tuple(Y.shape)} != ({self.n}, {self.m})")
+        if tuple(Y.shape) != self.shape():
+            raise ValueError(f"cube shape {tuple(Y.shape)} != {self.shape()} ({self.layout})")
         self.covariance(Y)
         self.eigh()
         self.project(Y)
@@ -102,8 +108,8 @@ class PCAStream:
         s = self.count % self.depth
         st = self.streams[s]
         pipe = self.pipes[s]
-        if tuple(Y.shape) != (pipe.n, pipe.m):
-            raise ValueError(f"cube shape {tuple(Y.shape)} != ({pipe.n}, {pipe.m})")
+        if tuple(Y.shape) != pipe.shape():
+            raise ValueError(f"cube shape {tuple(Y.shape)} != {pipe.shape()}")
         st.wait_stream(torch.cuda.current_stream())
         if self.chain and self.count > 0:
             st.wait_event(self.cov_done[(self.count - 1) % self.depth])
@@ -125,9 +131,11 @@ class PCAStream:
 
 
 def run(Y: torch.Tensor, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
-        max_sweeps: int = DEFAULT_MAX_SWEEPS, fp64_angles: bool = True) -> PCAResult:
-    """PCA of one device cube Y [pixels, bands] (float32 or uint16)."""
-    pipe = PCAPipeline(Y.shape[0], Y.shape[1], k, mode, tol, max_sweeps, fp64_angles, Y.device)
+        max_sweeps: int = DEFAULT_MAX_SWEEPS, fp64_angles: bool = True, layout: str = "bip") -> PCAResult:
+    """PCA of one device cube Y (float32 or uint16): [pixels, bands], or
+    [bands, pixels] with layout="bsq"."""
+    n, m = (Y.shape[1], Y.shape[0]) if layout == "bsq" else (Y.shape[0], Y.shape[1])
+    pipe = PCAPipeline(n, m, k, mode, tol, max_sweeps, fp64_angles, Y.device, layout=layout)
     return pipe.forward(Y)
 
 

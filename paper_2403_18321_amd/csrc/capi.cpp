@@ -13,13 +13,16 @@ inline size_t al(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
 
 inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-inline bool valid_dt(int dt) { return dt == PCA_IN_F32 || dt == PCA_IN_U16; }
+inline bool valid_dt(int dt) { return dt == PCA_IN_F32 || dt == PCA_IN_U16; }   // BIP
+inline bool is_bsq(int dt) { return dt == PCA_IN_F32_BSQ || dt == PCA_IN_U16_BSQ; }
 
+// A cube of either layout: ld is the stride between pixels (BIP, >= m) or
+// between bands (BSQ, >= n).
 inline pca_status check_cube(const void *Y, int dt, int64_t n, int32_t m, int64_t ld)
 {
-    if (!Y || !valid_dt(dt)) return PCA_ERR_ARG;
-    if (n < 2 || m < 2 || m > pca::kMaxBands || ld < m) return PCA_ERR_ARG;
-    if (!aligned(Y, dt == PCA_IN_F32 ? 4 : 2)) return PCA_ERR_ARG;
+    if (!Y || !(valid_dt(dt) || is_bsq(dt))) return PCA_ERR_ARG;
+    if (n < 2 || m < 2 || m > pca::kMaxBands || ld < (is_bsq(dt) ? n : (int64_t)m)) return PCA_ERR_ARG;
+    if (!aligned(Y, (dt == PCA_IN_F32 || dt == PCA_IN_F32_BSQ) ? 4 : 2)) return PCA_ERR_ARG;
     return PCA_OK;
 }
 
@@ -121,7 +124,7 @@ pca_status pca_center(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, 
     pca_status s = check_cube(Y, dt, n_pixels, n_bands, ld_y);
     if (s != PCA_OK) return s;
     if (!mean || !ws || !aligned(ws, kWsAlign) || !aligned(mean, 4)) return PCA_ERR_ARG;
-    if (X && (ld_x < n_bands || !aligned(X, 4))) return PCA_ERR_ARG;
+    if (X && (ld_x < (is_bsq(dt) ? n_pixels : (int64_t)n_bands) || !aligned(X, 4))) return PCA_ERR_ARG;
     const pca::CovPlan plan = pca::cov_plan(n_pixels, n_bands);
     if (ws_bytes < center_ws(plan, n_bands)) return PCA_ERR_WORKSPACE;
     char *w = static_cast<char *>(ws);
@@ -227,6 +230,7 @@ pca_status pca_batched(const pca_cube *cubes, const pca_cube *cubes_dev, int32_t
                        double tol, int32_t max_sweeps, int32_t fp64_angles, const pca_batch_tuning *tuning,
                        void *ws, size_t ws_bytes, void *stream)
 {
+    if (is_bsq(dt)) return PCA_ERR_UNSUPPORTED;   // the batched form takes BIP cubes
     if (!cubes_dev || !aligned(cubes_dev, 8) || !ws || !aligned(ws, kWsAlign) || !valid_dt(dt)) return PCA_ERR_ARG;
     if (mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
     if (!(tol >= 0.0) || !isfinite(tol) || (fp64_angles != 0 && fp64_angles != 1)) return PCA_ERR_ARG;

@@ -96,11 +96,67 @@ hipError_t launch_center_t(const T *Y, int64_t n, int m, int64_t ld, float *mean
     return hipGetLastError();
 }
 
+// Band-sequential cubes (Y[b * ld + p]): per chunk of pixels, each wave sums
+// whole band rows of the chunk (lanes along the row, coalesced), float64.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void center_sums_bsq_kernel(const T *__restrict__ Y, int64_t n, int m,
+                                                                   int64_t ld, int64_t chunk, int mpad,
+                                                                   double *__restrict__ partSum)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t c = blockIdx.x;
+    const int64_t pbeg = c * chunk;
+    const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
+    for (int b = wave; b < mpad; b += kThreads / 64) {
+        double t = 0.0;
+        if (b < m) {
+            const T *row = Y + (int64_t)b * ld;
+            for (int64_t p = pbeg + lane; p < pend; p += 64) t += (double)load_elem(row + p);
+        }
+        t = wave_sum(t);
+        if (lane == 0) partSum[c * mpad + b] = t;
+    }
+}
+
+// X[b * ldx + p] = Y[b * ld + p] - mu_b; grid (pixel blocks, bands).
+template <typename T>
+__global__ __launch_bounds__(256) void center_subtract_bsq_kernel(const T *__restrict__ Y, int64_t n, int64_t ld,
+                                                                  const double *__restrict__ mean64,
+                                                                  float *__restrict__ X, int64_t ldx)
+{
+    const int b = blockIdx.y;
+    const double mu = mean64[b];
+    const T *row = Y + (int64_t)b * ld;
+    float *out = X + (int64_t)b * ldx;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        out[p] = (float)((double)load_elem(row + p) - mu);
+}
+
+template <typename T>
+hipError_t launch_center_bsq(const T *Y, int64_t n, int m, int64_t ld, float *mean, float *X, int64_t ldx,
+                             const CovPlan &p, double *partSum, double *mean64, hipStream_t st)
+{
+    hipLaunchKernelGGL(center_sums_bsq_kernel<T>, dim3((unsigned)p.nchunks), dim3(kThreads), 0, st, Y, n, m, ld,
+                       p.chunk, p.mpad, partSum);
+    hipLaunchKernelGGL(center_mean_kernel, dim3(1), dim3(256), 0, st, n, m, p.nchunks, p.mpad, partSum, mean, mean64);
+    if (X) {
+        int64_t blocks = (n + 255) / 256;
+        if (blocks > 64) blocks = 64;
+        hipLaunchKernelGGL(center_subtract_bsq_kernel<T>, dim3((unsigned)blocks, (unsigned)m), dim3(256), 0, st, Y, n,
+                           ld, mean64, X, ldx);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_center(const void *Y, int dt, int64_t n, int m, int64_t ld, float *mean, float *X,
                          int64_t ldx, const CovPlan &plan, double *partSum, double *mean64, hipStream_t st)
 {
+    if (dt == PCA_IN_F32_BSQ)
+        return launch_center_bsq(static_cast<const float *>(Y), n, m, ld, mean, X, ldx, plan, partSum, mean64, st);
+    if (dt == PCA_IN_U16_BSQ)
+        return launch_center_bsq(static_cast<const uint16_t *>(Y), n, m, ld, mean, X, ldx, plan, partSum, mean64, st);
     const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32)
         return launch_center_t(static_cast<const float *>(Y), n, m, ld, mean, X, ldx, plan, partSum, mean64, st, v4);

@@ -548,6 +548,186 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     }
 }
 
+// ---- band-sequential cubes: Y[b * ld + p] --------------------------------
+//
+// The same chunk algorithm for cubes stored band by band (the layout of the
+// paper's GPU design, Section 4: BANDS x PIXELS, a band's pixels contiguous).
+// A stage is the chunk's next 32 pixels of every band, read row by row (16
+// lanes x 2 pixels cover one band's 32 pixels), and is already band-major,
+// the operand layout of the products, so centring and splitting are
+// elementwise: thread t holds pixels 2 (t mod 16), +1 of bands t / 16 + 32 j.
+// Loads run one stage ahead in registers. 8 waves; block ownership and the
+// bf16 products are those of cov_partial_dma_kernel (slot e of wave w: block
+// id idbase + 8 e + w), the float32 products read a band-major tile (pitch
+// 34 floats: the two half-waves of an operand read land on disjoint banks).
+// The float32 form keeps at most 3 slots (its two-level accumulators must
+// stay in registers) and covers wider matrices in several passes over the
+// cube, each with its own range of block ids.
+constexpr int kBsqPitchF = 34;
+
+template <typename T, int MODE, int S>
+__global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
+    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad, int idbase,
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+{
+    constexpr int kHalf = 256 * kBfPitch;
+    __shared__ __attribute__((aligned(16))) float tileF[MODE == MODE_F32 ? 256 * kBsqPitchF : 4];
+    __shared__ __attribute__((aligned(16))) __bf16 hl[MODE == MODE_F32 ? 8 : 2 * kHalf];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int pp = tid & 15;      // pixel pair within a stage
+    const int bg = tid >> 4;      // band group: bands bg + 32 j
+    const int64_t c = blockIdx.x;
+    const int64_t pbeg = c * chunk;
+    const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
+    const int64_t nst = (pend - pbeg + KT - 1) / KT;
+
+    // Shift: the chunk's first pixel, per band.
+    float sh[8];
+    double sums[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int b = bg + 32 * j;
+        sh[j] = b < m ? load_elem(Y + (int64_t)b * ld + pbeg) : 0.f;
+        sums[j] = 0.0;
+    }
+
+    constexpr bool kTwoLevel = MODE == MODE_F32;
+    constexpr int kSlots2 = kTwoLevel ? S : 1;
+    f32x16 acc[S], acc2[kSlots2];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[e][r] = 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < kSlots2; ++e) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc2[e][r] = 0.f;
+    }
+    const int nbl = nb * (nb + 1) / 2;
+    int offI[S], offJ[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        int bi = 0, bj = 0;
+        if (idbase + kDmaWaves * e + wave < nbl) block_of_id(idbase + kDmaWaves * e + wave, bi, bj);
+        if constexpr (MODE == MODE_F32) {
+            offI[e] = (32 * bi + (lane & 31)) * kBsqPitchF + (lane >> 5);
+            offJ[e] = (32 * bj + (lane & 31)) * kBsqPitchF + (lane >> 5);
+        } else {
+            offI[e] = (32 * bi + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
+            offJ[e] = (32 * bj + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
+        }
+    }
+
+    // Raw values of stage st for this thread (pixels past the chunk end and
+    // bands past the last one read as the shift, so they centre to zero).
+    auto load = [&](float (&v)[16], int64_t st) {
+        const int64_t p0 = pbeg + st * KT + 2 * pp;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int b = bg + 32 * j;
+            const T *row = Y + (int64_t)(b < m ? b : 0) * ld;
+            v[2 * j] = (b < m && p0 < pend) ? load_elem(row + p0) : sh[j];
+            v[2 * j + 1] = (b < m && p0 + 1 < pend) ? load_elem(row + p0 + 1) : sh[j];
+        }
+    };
+
+    auto stage = [&](const float (&v)[16], int64_t st) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int b = bg + 32 * j;
+            const float x0 = v[2 * j] - sh[j], x1 = v[2 * j + 1] - sh[j];
+            sums[j] += (double)(x0 + x1);
+            if (b < mpad) {
+                if constexpr (MODE == MODE_F32) {
+                    *reinterpret_cast<f32x2 *>(&tileF[b * kBsqPitchF + 2 * pp]) = f32x2{x0, x1};
+                } else {
+                    const f32x2 xv = {x0, x1};
+                    const bf16x2 hh = __builtin_convertvector(xv, bf16x2);
+                    const f32x2 r = xv - __builtin_convertvector(hh, f32x2);
+                    const bf16x2 ll = __builtin_convertvector(r, bf16x2);
+                    *reinterpret_cast<bf16x2 *>(&hl[b * kBfPitch + 2 * pp]) = hh;
+                    *reinterpret_cast<bf16x2 *>(&hl[kHalf + b * kBfPitch + 2 * pp]) = ll;
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (MODE == MODE_F32) {
+#pragma unroll 2
+            for (int kk = 0; kk < KT / 2; ++kk) {
+#pragma unroll
+                for (int e = 0; e < S; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(tileF[offI[e] + 2 * kk], tileF[offJ[e] + 2 * kk],
+                                                                 acc[e], 0, 0, 0);
+            }
+            if ((st + 1) % kFlush == 0) {
+#pragma unroll
+                for (int e = 0; e < S; ++e) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) { acc2[e][r] += acc[e][r]; acc[e][r] = 0.f; }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KT / 16; ++kk) {
+#pragma unroll
+                for (int e = 0; e < S; ++e) {
+                    const bf16x8 hi_i = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
+                    const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
+                    const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
+                    const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
+                    f32x16 a = acc[e];
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
+                    if constexpr (MODE == MODE_BF16X4)
+                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
+                    acc[e] = a;
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    float va[16], vb[16];
+    load(va, 0);
+    for (int64_t st = 0; st < nst; st += 2) {
+        if (st + 1 < nst) load(vb, st + 1);
+        stage(va, st);
+        if (st + 1 < nst) {
+            if (st + 2 < nst) load(va, st + 2);
+            stage(vb, st + 1);
+        }
+    }
+
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        if (idbase + kDmaWaves * e + wave < nbl) {
+            int bi, bj;
+            block_of_id(idbase + kDmaWaves * e + wave, bi, bj);
+            float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) dst[r * 64] = kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r];
+        }
+    }
+    // Band sums: the 16 threads of a band group (consecutive lanes) hold
+    // different pixels of the same bands.
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        double t = sums[j];
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) t += __shfl_xor(t, o, 16);
+        const int b = bg + 32 * j;
+        if (pp == 0 && b < mpad) {
+            partSum[c * mpad + b] = t;
+            partShift[c * mpad + b] = sh[j];
+        }
+    }
+}
+
 // Pass 2a: grid (block, chunk group). Every workgroup forms the band means of
 // its block's 64 bands (all chunks, float64, fixed order: identical in every
 // workgroup), then the centred second moment of its range of chunks.
@@ -782,6 +962,48 @@ hipError_t launch_dma_m(const float *Y, int64_t n, int m, int64_t ld, const CovP
     return hipGetLastError();
 }
 
+template <typename T, int MODE, int S>
+void launch_bsq_s(const T *Y, int64_t n, int m, int64_t ld, const CovPlan &p, int idbase, float *partS,
+                  double *partSum, float *partShift, hipStream_t st)
+{
+    hipLaunchKernelGGL((cov_partial_bsq_kernel<T, MODE, S>), dim3((unsigned)p.nchunks), dim3(kDmaThreads), 0, st, Y, n,
+                       m, ld, p.chunk, p.nb, p.nblk, p.mpad, idbase, partS, partSum, partShift);
+}
+
+template <typename T, int MODE>
+hipError_t launch_bsq_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS, double *partSum,
+                        float *partShift, hipStream_t st)
+{
+    const int slots = dma_slots(p.nb);
+    if (MODE == MODE_F32 && slots > 3) {
+        for (int base = 0; base < p.nblk; base += 3 * kDmaWaves)
+            launch_bsq_s<T, MODE, 3>(Y, n, m, ld, p, base, partS, partSum, partShift, st);
+        return hipGetLastError();
+    }
+    switch (slots) {
+    case 2: launch_bsq_s<T, MODE, 2>(Y, n, m, ld, p, 0, partS, partSum, partShift, st); break;
+    case 3: launch_bsq_s<T, MODE, 3>(Y, n, m, ld, p, 0, partS, partSum, partShift, st); break;
+    case 4:
+        if constexpr (MODE != MODE_F32) launch_bsq_s<T, MODE, 4>(Y, n, m, ld, p, 0, partS, partSum, partShift, st);
+        break;
+    default:
+        if constexpr (MODE != MODE_F32) launch_bsq_s<T, MODE, 5>(Y, n, m, ld, p, 0, partS, partSum, partShift, st);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_partial_bsq(const T *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p, float *partS,
+                              double *partSum, float *partShift, hipStream_t st)
+{
+    switch (mode) {
+    case MODE_F32: return launch_bsq_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    case MODE_BF16X3: return launch_bsq_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    default: return launch_bsq_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    }
+}
+
 hipError_t launch_partial_dma(const float *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p,
                               float *partS, double *partSum, float *partShift, hipStream_t st)
 {
@@ -832,6 +1054,11 @@ hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t l
                               int mode, const CovPlan &plan, float *partS, double *partSum,
                               float *partShift, hipStream_t st)
 {
+    if (dt == PCA_IN_F32_BSQ)
+        return launch_partial_bsq(static_cast<const float *>(Y), n, m, ld, mode, plan, partS, partSum, partShift, st);
+    if (dt == PCA_IN_U16_BSQ)
+        return launch_partial_bsq(static_cast<const uint16_t *>(Y), n, m, ld, mode, plan, partS, partSum, partShift,
+                                  st);
     const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32 && v4) return launch_partial_dma(static_cast<const float *>(Y), n, m, ld, mode, plan, partS,
                                                           partSum, partShift, st);

@@ -178,11 +178,68 @@ hipError_t launch_t(const T *Y, int64_t n, int m, int64_t ld, const float *mean,
     return hipGetLastError();
 }
 
+// Band-sequential cubes (Y[b * ld + p]): one thread per pixel, consecutive
+// threads on consecutive pixels so that every band row is read coalesced;
+// the block V[:, 16 g .. 16 g + 15] and the mean sit in LDS, where all lanes
+// read the same entry at a time (a broadcast). Float32 FMA chains per pixel,
+// bands in order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void project_bsq_kernel(const T *__restrict__ Y, int64_t n, int m, int64_t ld,
+                                                               const float *__restrict__ mean,
+                                                               const float *__restrict__ V, int k,
+                                                               float *__restrict__ Q)
+{
+    __shared__ __attribute__((aligned(16))) float vs[256][16];
+    __shared__ float mu[256];
+    const int g = blockIdx.y;
+    for (int e = threadIdx.x; e < 256 * 16; e += kThreads) {
+        const int b = e >> 4, o = 16 * g + (e & 15);
+        vs[b][e & 15] = (b < m && o < k) ? V[(int64_t)b * m + o] : 0.f;
+    }
+    for (int b = threadIdx.x; b < 256; b += kThreads) mu[b] = (mean && b < m) ? mean[b] : 0.f;
+    __syncthreads();
+    const int ncol = (k - 16 * g) < 16 ? (k - 16 * g) : 16;
+    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads) {
+        float acc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+        const T *col = Y + p;
+#pragma unroll 4
+        for (int b = 0; b < m; ++b) {
+            const float x = load_elem(col + (int64_t)b * ld) - mu[b];
+            const f32x4 *vr = reinterpret_cast<const f32x4 *>(vs[b]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f32x4 w = vr[q];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[4 * q + r] = fmaf(x, w[r], acc[4 * q + r]);
+            }
+        }
+        float *out = Q + p * k + 16 * g;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < ncol) out[j] = acc[j];
+    }
+}
+
+template <typename T>
+hipError_t launch_project_bsq(const T *Y, int64_t n, int m, int64_t ld, const float *mean, const float *V, int k,
+                              float *Q, hipStream_t st)
+{
+    int64_t blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(project_bsq_kernel<T>, dim3((unsigned)blocks, (unsigned)((k + 15) / 16)), dim3(kThreads), 0,
+                       st, Y, n, m, ld, mean, V, k, Q);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_project(const void *Y, int dt, int64_t n, int m, int64_t ld, const float *mean,
                           const float *V, int k, float *Q, hipStream_t st)
 {
+    if (dt == PCA_IN_F32_BSQ) return launch_project_bsq(static_cast<const float *>(Y), n, m, ld, mean, V, k, Q, st);
+    if (dt == PCA_IN_U16_BSQ) return launch_project_bsq(static_cast<const uint16_t *>(Y), n, m, ld, mean, V, k, Q, st);
     const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32) return launch_t(static_cast<const float *>(Y), n, m, ld, mean, V, k, Q, st, v4);
     return launch_t(static_cast<const uint16_t *>(Y), n, m, ld, mean, V, k, Q, st, v4);

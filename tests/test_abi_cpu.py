@@ -77,6 +77,12 @@ def test_invalid_arguments_rejected_on_host(lib):
     # Workspace too small.
     assert so.pca_covariance(fake, 0, 100000, 64, 64, 0, null, 0, fake, fake, 256,
                              null) == lib.PCA_ERR_WORKSPACE
+    # Band-sequential: the band stride must cover the pixels (not the bands).
+    assert so.pca_covariance(fake, lib.PCA_IN_F32_BSQ, 100, 8, 99, 0, null, 0, fake, fake, 1 << 20, null) == ARG
+    assert so.pca_covariance(fake, lib.PCA_IN_U16_BSQ, 100, 8, 8, 0, null, 0, fake, fake, 1 << 20, null) == ARG
+    assert so.pca_project(fake, lib.PCA_IN_F32_BSQ, 100, 8, 50, null, fake, 2, fake, null) == ARG
+    assert so.pca_center(fake, lib.PCA_IN_F32_BSQ, 100, 8, 100, fake, fake, 8, fake, 1 << 20, null) == ARG
+    assert so.pca_covariance(fake, 4, 100, 8, 100, 0, null, 0, fake, fake, 1 << 20, null) == ARG
     # Jacobi: negative tolerance, too many bands, misaligned workspace.
     assert so.pca_jacobi_eigh(fake, 8, -1.0, 10, 1, fake, fake, null, fake, 1 << 20, null) == ARG
     assert so.pca_jacobi_eigh(fake, 300, 1e-6, 10, 1, fake, fake, null, fake, 1 << 20, null) == ARG
@@ -119,6 +125,8 @@ def test_batched_arguments_rejected_on_host(lib):
     arr[1].k = 40
     assert ok(cubes, dev, 2, 0, 0, 1e-6, 30, 1, null, ws, need, null) == ARG
     arr[1].k = 3
+    # Band-sequential cubes are not taken by the batched form.
+    assert ok(cubes, dev, 2, lib.PCA_IN_F32_BSQ, 0, 1e-6, 30, 1, null, ws, need, null) == lib.PCA_ERR_UNSUPPORTED
     # Tuning: chunk not a multiple of 32.
     t = lib.PCABatchTuning(100, 4)
     assert so.pca_batched(cubes, dev, 2, 0, 0, 1e-6, 30, 1, ctypes.cast(ctypes.pointer(t), ctypes.c_void_p), ws,
