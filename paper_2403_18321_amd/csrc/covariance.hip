@@ -329,23 +329,30 @@ __device__ __forceinline__ void lds_barrier()
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 
-template <int MODE, int S>
+template <typename T, int MODE, int S>
 __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
-    const float *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
+    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
     float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
 {
-    // Staged pixel rows: 256 floats (288 for the float32 products, whose two
-    // half-waves read rows one apart).
-    constexpr int pitch = MODE == MODE_F32 ? 288 : 256;
-    constexpr int kRawFloats = KT * pitch;
+    // Staged pixel rows of 256 elements (288 floats for the float32 products
+    // of a float32 cube, whose two half-waves read rows one apart). A copy
+    // instruction moves 16 bytes per lane: one float32 row (4 bands a lane),
+    // or two uint16 rows (8 bands a lane, lanes 32-63 on the second pixel).
+    constexpr bool kU16 = sizeof(T) == 2;
+    constexpr int pitch = (MODE == MODE_F32 && !kU16) ? 288 : 256;
+    constexpr int kPerLane = 16 / (int)sizeof(T);            // bands per lane and copy
+    constexpr int kRowsPerCopy = kU16 ? 2 : 1;
+    constexpr int kCopies = kDmaPix / kRowsPerCopy;          // copies per wave per stage
+    constexpr int kRawElems = KT * pitch;
     constexpr int kHalf = 256 * kBfPitch;   // bf16 per tile (hi, then lo)
-    __shared__ __attribute__((aligned(16))) float raw0[kRawFloats];
-    __shared__ __attribute__((aligned(16))) float raw1[kRawFloats];
-    __shared__ __attribute__((aligned(16))) float raw2[kRawFloats];
+    constexpr int kRawWords = (kRawElems * (int)sizeof(T) + 3) / 4;
+    __shared__ __attribute__((aligned(16))) T raw0[kRawElems];
+    __shared__ __attribute__((aligned(16))) T raw1[kRawElems];
+    __shared__ __attribute__((aligned(16))) T raw2[kRawElems];
     __shared__ __attribute__((aligned(16))) __bf16 hl[MODE == MODE_F32 ? 8 : 2 * kHalf];
     __shared__ float shv[256];
-    static_assert(kRawFloats * sizeof(float) >= kDmaWaves * 256 * sizeof(double), "band-sum scratch");
-    double(*red)[256] = reinterpret_cast<double(*)[256]>(raw0);   // used after the ring is drained
+    static_assert(kRawWords * 4 >= kDmaWaves * 256 * (int)sizeof(double), "band-sum scratch");
+    double(*red)[256] = reinterpret_cast<double(*)[256]>(static_cast<void *>(raw0));   // after the ring drains
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -354,8 +361,9 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     const int64_t pbeg = c * chunk;
     const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
     const int64_t nst = (pend - pbeg + KT - 1) / KT;
-    const int loff = 4 * lane < m ? 4 * lane : 0;   // m % 4 == 0 on this path
-    const float *row0 = Y + pbeg * ld;
+    const int cl = kU16 ? (lane & 31) : lane;                  // lane within its row
+    const int loff = kPerLane * cl < m ? kPerLane * cl : 0;   // m % kPerLane == 0 on this path
+    const T *row0 = Y + pbeg * ld;
 
     // Workgroups walk their chunks from different starting stages (evenly
     // spread over the chunk, wrapping around): chunks are equal power-of-two
@@ -365,21 +373,23 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     // Copies of the stage at position t of this walk (pixels pbeg + 32 t'
     // with t' = (t + rot) mod nst; positions past the end copy the first
     // pixel) into ring slot R.
-    auto issue = [&](float *R, int64_t t) {
+    auto issue = [&](T *R, int64_t t) {
         const int64_t tt = t < nst ? (t + rot < nst ? t + rot : t + rot - nst) : nst;
 #pragma unroll
-        for (int i = 0; i < kDmaPix; ++i) {
-            const int64_t p = pbeg + tt * KT + kDmaPix * wave + i;
-            const float *rowp = (p < pend && loff == 4 * lane) ? Y + p * ld : row0;
-            __builtin_amdgcn_global_load_lds(rowp + loff, R + (kDmaPix * wave + i) * pitch, 16, 0, 0);
+        for (int i = 0; i < kCopies; ++i) {
+            const int r = kDmaPix * wave + kRowsPerCopy * i;           // first staged row of this copy
+            const int64_t p = pbeg + tt * KT + r + (kU16 ? (lane >> 5) : 0);
+            const T *rowp = (p < pend && loff == kPerLane * cl) ? Y + p * ld : row0;
+            // (void pointers: the host pass drops kernels whose target
+            // builtins take arguments of template-dependent type)
+            __builtin_amdgcn_global_load_lds(static_cast<const void *>(rowp + loff), static_cast<void *>(R + r * pitch),
+                                             16, 0, 0);
         }
     };
 
-    const f32x4 shift = *reinterpret_cast<const f32x4 *>(row0 + loff);
-    if (wave == 0) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) shv[4 * lane + s] = shift[s];
-    }
+    // Shift per band: the first pixel; bands past the last one take the
+    // values their lanes copy (row0[b mod kPerLane]), so they centre to zero.
+    for (int b = tid; b < 256; b += kDmaThreads) shv[b] = load_elem(row0 + (b < m ? b : b % kPerLane));
     asm volatile("" ::: "memory");   // the shift load and store stay ahead of the copies
     issue(raw0, 0);
     issue(raw1, 1);
@@ -433,14 +443,14 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     // This wave's pixels of a landed stage, centred: band sums (float32 over
     // the stage's 4 pixels, then float64) and, for the split forms, the hi /
     // lo tiles in LDS, band-major.
-    auto centre = [&](const float *R) {
+    auto centre = [&](const T *R) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int b = lane + 64 * s;
             if (b >= mpad) continue;
             float x[kDmaPix];
 #pragma unroll
-            for (int i = 0; i < kDmaPix; ++i) x[i] = R[(kDmaPix * wave + i) * pitch + b] - shb[s];
+            for (int i = 0; i < kDmaPix; ++i) x[i] = load_elem(R + (kDmaPix * wave + i) * pitch + b) - shb[s];
             sums[s] += (double)((x[0] + x[1]) + (x[2] + x[3]));
             if constexpr (MODE != MODE_F32) {
                 bf16x4 h, l;
@@ -461,15 +471,15 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
         }
     };
 
-    auto products = [&](const float *R) {
+    auto products = [&](const T *R) {
         if constexpr (MODE == MODE_F32) {
 #pragma unroll 2
             for (int kk = 0; kk < KT / 2; ++kk) {
-                const float *tr = R + (2 * kk + (lane >> 5)) * pitch;
+                const T *tr = R + (2 * kk + (lane >> 5)) * pitch;
 #pragma unroll
                 for (int e = 0; e < S; ++e)
-                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(tr[offI[e]] - shI[e], tr[offJ[e]] - shJ[e], acc[e],
-                                                                 0, 0, 0);
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(load_elem(tr + offI[e]) - shI[e],
+                                                                 load_elem(tr + offJ[e]) - shJ[e], acc[e], 0, 0, 0);
             }
         } else {
 #pragma unroll
@@ -498,8 +508,8 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     // a multiple of the ring: stages past the chunk end are copies of its
     // first pixel, which centre to exact zeros and add nothing, so every step
     // is the same straight-line code with one copy wait.
-    auto step = [&](float *cur, float *nxt, int64_t st) {
-        __builtin_amdgcn_s_waitcnt(waitcnt_vm(kDmaPix));
+    auto step = [&](T *cur, T *nxt, int64_t st) {
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(kCopies));
         lds_barrier();
         issue(nxt, st + 2);
         centre(cur);
@@ -936,26 +946,26 @@ hipError_t launch_partial_m(const T *Y, int64_t n, int m, int64_t ld, int center
     return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t launch_dma_m(const float *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
+template <typename T, int MODE>
+hipError_t launch_dma_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
                         double *partSum, float *partShift, hipStream_t st)
 {
     dim3 grid((unsigned)p.nchunks), block(kDmaThreads);
     switch (dma_slots(p.nb)) {
     case 2:
-        hipLaunchKernelGGL((cov_partial_dma_kernel<MODE, 2>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
+        hipLaunchKernelGGL((cov_partial_dma_kernel<T, MODE, 2>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
                            p.mpad, partS, partSum, partShift);
         break;
     case 3:
-        hipLaunchKernelGGL((cov_partial_dma_kernel<MODE, 3>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
+        hipLaunchKernelGGL((cov_partial_dma_kernel<T, MODE, 3>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
                            p.mpad, partS, partSum, partShift);
         break;
     case 4:
-        hipLaunchKernelGGL((cov_partial_dma_kernel<MODE, 4>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
+        hipLaunchKernelGGL((cov_partial_dma_kernel<T, MODE, 4>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
                            p.mpad, partS, partSum, partShift);
         break;
     default:
-        hipLaunchKernelGGL((cov_partial_dma_kernel<MODE, 5>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
+        hipLaunchKernelGGL((cov_partial_dma_kernel<T, MODE, 5>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
                            p.mpad, partS, partSum, partShift);
         break;
     }
@@ -1004,14 +1014,23 @@ hipError_t launch_partial_bsq(const T *Y, int64_t n, int m, int64_t ld, int mode
     }
 }
 
-hipError_t launch_partial_dma(const float *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p,
+template <typename T>
+hipError_t launch_partial_dma(const T *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p,
                               float *partS, double *partSum, float *partShift, hipStream_t st)
 {
     switch (mode) {
-    case MODE_F32: return launch_dma_m<MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, st);
-    case MODE_BF16X3: return launch_dma_m<MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
-    default: return launch_dma_m<MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    case MODE_F32: return launch_dma_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    case MODE_BF16X3: return launch_dma_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    default: return launch_dma_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
     }
+}
+
+// Rows that the 16-byte copies can stage: 16-byte aligned, with whole lanes
+// (4 float32 or 8 uint16 bands) per row.
+inline bool dma_ok(const void *Y, int dt, int m, int64_t ld)
+{
+    const int per = dt == PCA_IN_F32 ? 4 : 8;
+    return (reinterpret_cast<uintptr_t>(Y) % 16 == 0) && m % per == 0 && ld % per == 0;
 }
 
 template <typename T, int VEC>
@@ -1059,9 +1078,14 @@ hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t l
     if (dt == PCA_IN_U16_BSQ)
         return launch_partial_bsq(static_cast<const uint16_t *>(Y), n, m, ld, mode, plan, partS, partSum, partShift,
                                   st);
+    if (dma_ok(Y, dt, m, ld)) {
+        if (dt == PCA_IN_F32)
+            return launch_partial_dma(static_cast<const float *>(Y), n, m, ld, mode, plan, partS, partSum, partShift,
+                                      st);
+        return launch_partial_dma(static_cast<const uint16_t *>(Y), n, m, ld, mode, plan, partS, partSum, partShift,
+                                  st);
+    }
     const bool v4 = vec4_ok(Y, dt, m, ld);
-    if (dt == PCA_IN_F32 && v4) return launch_partial_dma(static_cast<const float *>(Y), n, m, ld, mode, plan, partS,
-                                                          partSum, partShift, st);
     if (dt == PCA_IN_F32) {
         const float *y = static_cast<const float *>(Y);
         return v4 ? launch_partial_t<float, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st)

@@ -88,6 +88,25 @@ def test_covariance_strided_and_u16(pca):
     assert np.abs(C - ref["C"]).max() / np.abs(ref["C"]).max() <= COV_TOL["f32"]
 
 
+@pytest.mark.parametrize("n,m,pad", [(1000, 8, 0), (3001, 96, 0), (20001, 224, 0), (4099, 256, 8), (2500, 104, 16)])
+def test_covariance_u16_rows_staged_in_lds(pca, n, m, pad):
+    """uint16 cubes whose rows the 16-byte copies can stage (bands and row
+    stride multiples of 8): two pixel rows per copy instruction."""
+    say(f"covariance uint16 copy path n={n} m={m} pad={pad}")
+    u = synth.radiance_cube_u16(np.random.default_rng(900 + m), n, m, 6, 1.0)
+    ref = oracle.pca(u, 1)
+    buf = np.zeros((n, m + pad), dtype=np.uint16)
+    buf[:, :m] = u
+    Yd = dev(buf)[:, :m] if pad else dev(u)
+    for mode in ("f32", "bf16x3", "bf16x4"):
+        C, mean = gpu_cov(pca, Yd, mode)
+        err = np.abs(C - ref["C"]).max() / np.abs(ref["C"]).max()
+        say(f"  {mode}: {err:.2e}")
+        assert err <= COV_TOL[mode], (mode, err)
+        assert np.array_equal(C, C.T)
+        assert np.abs(mean - ref["mean"]).max() <= 1e-6 * ref["mean"].max()
+
+
 def test_covariance_centered_flag(pca):
     say("covariance centred input")
     rng = np.random.default_rng(8)
