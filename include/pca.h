@@ -79,6 +79,19 @@ typedef enum {
     PCA_OP_BACKWARD = 4
 } pca_op;
 
+/* Flags of pca_jacobi_eigh. */
+typedef enum {
+    /* Rotation angles and the updated diagonal in float64 (else float32). */
+    PCA_JACOBI_FP64_ANGLES = 1,
+    /* Form the eigenvectors (the product of the rotations, equation (10))
+     * while the sweeps run, on other CUs of the same launch, instead of
+     * after them: the same results bit for bit, without the replay's time
+     * after the sweeps; it holds one more CU per ~2048/n_bands rows of the
+     * eigenvector matrix for the length of the sweeps, so it pays when one
+     * cube has the GPU to itself. */
+    PCA_JACOBI_OVERLAP_REPLAY = 2
+} pca_jacobi_flag;
+
 /* Written on the device by pca_jacobi_eigh (copy it back to read it). */
 typedef struct {
     int32_t sweeps;      /* sweeps carried out */
@@ -161,8 +174,8 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
  * n_bands/2 disjoint rotations per parallel step in round-robin order (the
  * parallel-rotation property stated at the end of Section 2), n_bands - 1
  * steps per sweep. Rotation angles use equations (2)-(5) with (7) in the
- * cancellation-free form; fp64_angles = 1 evaluates them (and the diagonal)
- * in float64. A rotation is skipped when |a_pq| <= 2^-24 sqrt(|a_pp a_qq|)
+ * cancellation-free form; the flag PCA_JACOBI_FP64_ANGLES evaluates them
+ * (and the diagonal) in float64. A rotation is skipped when |a_pq| <= 2^-24 sqrt(|a_pp a_qq|)
  * or |a_pq| <= 2^-24 ||C||_F / n_bands. Stops before a sweep when
  * off(A)/||C||_F <= tol, after a sweep that applied no rotation, or after
  * max_sweeps sweeps.
@@ -173,10 +186,16 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
  *   eigvals  [n_bands] float32 out, descending.
  *   V        [n_bands][n_bands] float32 out; column j is eigenvector j.
  *   info     device pca_info out (may be NULL).
+ *   flags    OR of pca_jacobi_flag values (other bits: PCA_ERR_ARG).
  *   ws       workspace of pca_workspace_size(PCA_OP_JACOBI, ..., max_sweeps).
+ *            The first call with PCA_JACOBI_OVERLAP_REPLAY on a workspace
+ *            needs it zero-filled (once, at allocation: its rotation log is
+ *            read while it is written, and every call leaves the log zeroed
+ *            for the next); calls that share a workspace must not overlap in
+ *            time.
  */
 pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t max_sweeps,
-                           int32_t fp64_angles, float *eigvals, float *V, pca_info *info,
+                           int32_t flags, float *eigvals, float *V, pca_info *info,
                            void *ws, size_t ws_bytes, void *stream);
 
 /*

@@ -14,6 +14,8 @@ from ._lib import (  # noqa: F401
     PCA_IN_U16,
     PCA_IN_F32_BSQ,
     PCA_IN_U16_BSQ,
+    PCA_JACOBI_FP64_ANGLES,
+    PCA_JACOBI_OVERLAP_REPLAY,
     PCA_OP_CENTER,
     PCA_OP_COVARIANCE,
     PCA_OP_JACOBI,

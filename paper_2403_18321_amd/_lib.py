@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libpca.so")
 PCA_OK, PCA_ERR_ARG, PCA_ERR_UNSUPPORTED, PCA_ERR_WORKSPACE, PCA_ERR_HIP = range(5)
 PCA_IN_F32, PCA_IN_U16, PCA_IN_F32_BSQ, PCA_IN_U16_BSQ = 0, 1, 2, 3
 PCA_COV_F32, PCA_COV_BF16X3, PCA_COV_BF16X4 = 0, 1, 2
+PCA_JACOBI_FP64_ANGLES, PCA_JACOBI_OVERLAP_REPLAY = 1, 2
 PCA_OP_CENTER, PCA_OP_COVARIANCE, PCA_OP_JACOBI, PCA_OP_PROJECT, PCA_OP_BACKWARD = range(5)
 
 COV_MODES = {"f32": PCA_COV_F32, "bf16x3": PCA_COV_BF16X3, "bf16x4": PCA_COV_BF16X4}
@@ -139,9 +140,10 @@ def pca_workspace_size(op: int, n_pixels: int, n_bands: int, k: int = 1, mode: i
 
 
 def workspace(nbytes: int, device=None) -> torch.Tensor:
-    """A device byte buffer for a workspace argument (torch allocations are
-    at least 256-byte aligned)."""
-    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+    """A zero-filled device byte buffer for a workspace argument (torch
+    allocations are at least 256-byte aligned; the Jacobi call's overlapped
+    replay wants its workspace zero-filled before first use)."""
+    return torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
 
 
 def pca_center(Y, mean, X=None, ws=None, layout: str = "bip"):
@@ -162,11 +164,15 @@ def pca_covariance(Y, C, mean=None, mode: int = PCA_COV_F32, input_is_centered: 
                                                    int(mode), _ptr(C), _ptr(ws), ws.numel(), _stream()))
 
 
-def pca_jacobi_eigh(C, eigvals, V, tol: float, max_sweeps: int, fp64_angles: bool = True, info=None, ws=None):
+def pca_jacobi_eigh(C, eigvals, V, tol: float, max_sweeps: int, fp64_angles: bool = True, info=None, ws=None,
+                    overlap: bool = False):
+    """overlap: PCA_JACOBI_OVERLAP_REPLAY (eigenvectors formed while the
+    sweeps run; bitwise the same results)."""
     m = C.shape[0]
     if ws is None:
         ws = workspace(pca_workspace_size(PCA_OP_JACOBI, 2, m, max_sweeps=max_sweeps), C.device)
-    _check("pca_jacobi_eigh", _lib().pca_jacobi_eigh(_ptr(C), m, float(tol), int(max_sweeps), int(bool(fp64_angles)),
+    flags = (PCA_JACOBI_FP64_ANGLES if fp64_angles else 0) | (PCA_JACOBI_OVERLAP_REPLAY if overlap else 0)
+    _check("pca_jacobi_eigh", _lib().pca_jacobi_eigh(_ptr(C), m, float(tol), int(max_sweeps), flags,
                                                      _ptr(eigvals), _ptr(V), _ptr(info), _ptr(ws), ws.numel(),
                                                      _stream()))
 

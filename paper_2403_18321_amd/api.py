@@ -33,13 +33,17 @@ class PCAPipeline:
 
     def __init__(self, n_pixels: int, n_bands: int, k: int, mode: str = "f32",
                  tol: float = DEFAULT_TOL, max_sweeps: int = DEFAULT_MAX_SWEEPS,
-                 fp64_angles: bool = True, device="cuda", layout: str = "bip"):
+                 fp64_angles: bool = True, device="cuda", layout: str = "bip", overlap_replay: bool = True):
         """layout: "bip" for [pixels, bands] cubes, "bsq" for [bands, pixels]
-        (band-sequential) cubes."""
+        (band-sequential) cubes. overlap_replay: form the eigenvectors while
+        the Jacobi sweeps run, on other CUs of the same launch (for a cube
+        that has the GPU to itself; a stream of cubes leaves those CUs to
+        the other cubes' passes)."""
         self.n, self.m, self.k = int(n_pixels), int(n_bands), int(k)
         self.layout = layout
         self.mode = L.COV_MODES[mode] if isinstance(mode, str) else int(mode)
         self.tol, self.max_sweeps, self.fp64_angles = float(tol), int(max_sweeps), bool(fp64_angles)
+        self.overlap_replay = bool(overlap_replay)
         dev = torch.device(device)
         f32 = dict(dtype=torch.float32, device=dev)
         self.mean = torch.empty(self.m, **f32)
@@ -57,7 +61,7 @@ class PCAPipeline:
 
     def eigh(self):
         L.pca_jacobi_eigh(self.C, self.eigvals, self.V, self.tol, self.max_sweeps, self.fp64_angles,
-                          self.info, self.ws_jac)
+                          self.info, self.ws_jac, overlap=self.overlap_replay)
 
     def project(self, Y):
         L.pca_project(Y, self.mean, self.V, self.k, self.Q, layout=self.layout)
@@ -90,13 +94,13 @@ class PCAStream:
 
     def __init__(self, n_pixels: int, n_bands: int, k: int, mode: str = "f32", depth: int = 4,
                  tol: float = DEFAULT_TOL, max_sweeps: int = DEFAULT_MAX_SWEEPS,
-                 fp64_angles: bool = True, device="cuda", chain: bool = True):
+                 fp64_angles: bool = True, device="cuda", chain: bool = True, overlap_replay: bool = False):
         if depth < 1:
             raise ValueError("depth must be >= 1")
         self.depth = int(depth)
         self.chain = bool(chain)
-        self.pipes = [PCAPipeline(n_pixels, n_bands, k, mode, tol, max_sweeps, fp64_angles, device)
-                      for _ in range(self.depth)]
+        self.pipes = [PCAPipeline(n_pixels, n_bands, k, mode, tol, max_sweeps, fp64_angles, device,
+                                  overlap_replay=overlap_replay) for _ in range(self.depth)]
         self.streams = [torch.cuda.Stream(device=device) for _ in range(self.depth)]
         self.events = [torch.cuda.Event() for _ in range(self.depth)]
         self.cov_done = [torch.cuda.Event() for _ in range(self.depth)]
@@ -131,11 +135,13 @@ class PCAStream:
 
 
 def run(Y: torch.Tensor, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
-        max_sweeps: int = DEFAULT_MAX_SWEEPS, fp64_angles: bool = True, layout: str = "bip") -> PCAResult:
+        max_sweeps: int = DEFAULT_MAX_SWEEPS, fp64_angles: bool = True, layout: str = "bip",
+        overlap_replay: bool = True) -> PCAResult:
     """PCA of one device cube Y (float32 or uint16): [pixels, bands], or
     [bands, pixels] with layout="bsq"."""
     n, m = (Y.shape[1], Y.shape[0]) if layout == "bsq" else (Y.shape[0], Y.shape[1])
-    pipe = PCAPipeline(n, m, k, mode, tol, max_sweeps, fp64_angles, Y.device, layout=layout)
+    pipe = PCAPipeline(n, m, k, mode, tol, max_sweeps, fp64_angles, Y.device, layout=layout,
+                       overlap_replay=overlap_replay)
     return pipe.forward(Y)
 
 

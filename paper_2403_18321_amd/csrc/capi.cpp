@@ -30,7 +30,10 @@ inline pca_status hip_status(hipError_t e) { return e == hipSuccess ? PCA_OK : P
 
 size_t center_ws(const pca::CovPlan &p, int m) { return al(p.bytes_sum) + al((size_t)m * sizeof(double)); }
 size_t cov_ws(const pca::CovPlan &p) { return al(p.bytes_S) + al(p.bytes_sum) + al(p.bytes_shift) + al(p.bytes_part2); }
-size_t jac_ws(const pca::JacPlan &p) { return al(p.bytes_log) + al(p.bytes_lam) + al(p.bytes_vu) + al(p.bytes_info); }
+size_t jac_ws(const pca::JacPlan &p)
+{
+    return al(p.bytes_log) + al(p.bytes_lam) + al(p.bytes_vu) + al(p.bytes_info);
+}
 size_t bwd_ws(const pca::BwdPlan &p) { return al(p.bytes_part) + al(p.bytes_w) + al(p.bytes_sums) + al(p.bytes_g); }
 
 // Host-side checks and sizes of a batch; fills the six launch totals.
@@ -158,13 +161,13 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
                                                partShift, part2, C, mean, st));
 }
 
-pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t max_sweeps, int32_t fp64_angles,
+pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t max_sweeps, int32_t flags,
                            float *eigvals, float *V, pca_info *info, void *ws, size_t ws_bytes, void *stream)
 {
     if (!C || !eigvals || !V || !ws) return PCA_ERR_ARG;
     if (n_bands < 2 || n_bands > pca::kMaxBands) return PCA_ERR_ARG;
     if (!(tol >= 0.0) || !isfinite(tol) || max_sweeps < 0 || max_sweeps > 100000) return PCA_ERR_ARG;
-    if (fp64_angles != 0 && fp64_angles != 1) return PCA_ERR_ARG;
+    if (flags & ~(PCA_JACOBI_FP64_ANGLES | PCA_JACOBI_OVERLAP_REPLAY)) return PCA_ERR_ARG;
     if (!aligned(ws, kWsAlign) || !aligned(C, 4) || !aligned(eigvals, 4) || !aligned(V, 4)) return PCA_ERR_ARG;
     if (info && !aligned(info, 8)) return PCA_ERR_ARG;
     const pca::JacPlan plan = pca::jac_plan(n_bands, max_sweeps);
@@ -177,8 +180,9 @@ pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t 
     float *Vu = reinterpret_cast<float *>(w);
     w += al(plan.bytes_vu);
     pca_info *info_ws = reinterpret_cast<pca_info *>(w);
-    return hip_status(pca::launch_jacobi(C, n_bands, tol, max_sweeps, fp64_angles, plan, lam_u, rlog, Vu, info_ws,
-                                         eigvals, V, info, static_cast<hipStream_t>(stream)));
+    return hip_status(pca::launch_jacobi(C, n_bands, tol, max_sweeps, flags & PCA_JACOBI_FP64_ANGLES,
+                                         (flags & PCA_JACOBI_OVERLAP_REPLAY) ? 1 : 0, plan, lam_u, rlog, Vu,
+                                         info_ws, eigvals, V, info, static_cast<hipStream_t>(stream)));
 }
 
 pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,

@@ -41,6 +41,22 @@
 // Rows of E evolve independently under E <- E P; each workgroup replays the
 // whole log on a few rows, in the same slot coordinates.
 //
+// jacobi_follow_kernel: the same two computations in one launch. Workgroup 0
+// runs the Jacobi sweeps; workgroups 1.. replay the rotation log on their
+// rows of E while it is being written, so that the replay ends a batch or so
+// after the last rotation instead of starting then. The log entries validate
+// themselves: the log starts zeroed, a real entry has cos >= 1/sqrt(2) > 0,
+// and after the last step the Jacobi workgroup fills the rest of the current
+// kLogBatch-step batch with end marks (cos = -1). A follower waits until every
+// entry of its next batch is non-zero (each entry is written once per call,
+// so its first non-zero value is final), replays the steps before the first
+// end mark and stops there. Entries go through agent-scope coherent stores
+// and loads, which are visible across the chip's separate L2 caches without
+// cache flushes or fences. sort_sign_kernel, the next launch, zeroes the used
+// part of the log again. The Jacobi workgroup never waits for the followers,
+// and a follower that sees an entry stay zero for about a second writes NaN
+// rows and exits, so every workgroup ends.
+//
 // sort_sign_kernel: eigenvalues from the diagonal, sorted in descending order
 // (stable), eigenvector columns permuted to match (Code 4.4.3), and the sign
 // of each column fixed so its largest-magnitude entry is positive.
@@ -60,6 +76,25 @@ constexpr int kBlockPad = 32;         // tail that segment reads may run into
 constexpr int kCsPad = 32;
 constexpr int kLoadPerThread = 16;    // loads in flight per pass
 constexpr double kFloorRel2 = 3.552713678800501e-15;   // (2^-24)^2
+constexpr float kLogEnd = -1.f;       // cos of an end mark in the rotation log
+
+// The matrix blocks of the Jacobi workgroup; a follower workgroup of the
+// same launch uses the same LDS for its rows of E and its log batch.
+__shared__ float4 jac_blk[kMaxRowBlocks + kBlockPad];
+
+__device__ inline void log_store(float2 *p, float2 v)
+{
+    const unsigned long long bits =
+        (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), bits, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline float2 log_load(const float2 *p)
+{
+    const unsigned long long bits = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((unsigned int)bits), __uint_as_float((unsigned int)(bits >> 32)));
+}
 
 struct Slots {
     int P, n;
@@ -224,14 +259,16 @@ __device__ inline int block_sum_i(int v, int *red)
 //   one special block (the diagonals next to the pivots and the last column),
 //     with explicit destination codes; a special block that produces a pivot
 //     of the next step also computes that pivot's rotation;
-//   thread j < P moves pair j's rotated pivot to its next place and logs the
-//     rotation.
-template <int L>
+//   thread j < P moves pair j's rotated pivot to its next place;
+//   thread 1024 - P + j logs pair j's rotation.
+// kFollow: the rotation log is read while it is written (coherent stores,
+// end marks after the last step).
+template <int L, bool kFollow>
 __device__ __forceinline__ void jacobi_body(const float *__restrict__ C, int m, int n, double tol, int max_sweeps,
                                    int fp64_angles, double *__restrict__ lam_u, float2 *__restrict__ rlog,
                                    pca_info *__restrict__ info)
 {
-    __shared__ float4 blk[kMaxRowBlocks + kBlockPad];
+    float4 *blk = jac_blk;
     __shared__ double dg[2][256];
     __shared__ float2 csb[2][kMaxP + kCsPad];   // (tan, cos) of each pair's rotation
     __shared__ float pvb[2][kMaxP];             // pivot after its rotation (0 unless skipped)
@@ -485,10 +522,18 @@ __device__ __forceinline__ void jacobi_body(const float *__restrict__ C, int m, 
                     rotate(mine1, pv, par ^ 1, par, par ^ 1);
                 }
             }
-            if (tid < P) {
-                const float2 tc = cs[tid];
+            // The last P threads (the waves with the least work in a step)
+            // log the step's rotations, so that no global store and no wait
+            // for one sits in the waves on the step's critical path.
+            if (tid >= kJThreads - P) {
+                const int j = tid - (kJThreads - P);
+                const float2 tc = cs[j];
                 cnt += tc.x != 0.f;
-                rlog[g * P + tid] = make_float2(tc.y, tc.x * tc.y);
+                const float2 e = make_float2(tc.y, tc.x * tc.y);
+                if (kFollow) log_store(&rlog[g * P + j], e);
+                else rlog[g * P + j] = e;
+            }
+            if (tid < P) {
                 const float pv = pvb[par][tid];
                 if (pcode >= 0) {
                     Af[pcode] = pv;
@@ -505,6 +550,11 @@ __device__ __forceinline__ void jacobi_body(const float *__restrict__ C, int m, 
         if (applied == 0) { converged = 1; floor_hit = 1; break; }
     }
 
+    if (kFollow) {
+        // End marks from step g to the end of its batch.
+        const int64_t ends = (g / kLogBatch + 1) * kLogBatch - g;
+        for (int64_t t = tid; t < ends * P; t += kJThreads) log_store(&rlog[g * P + t], make_float2(kLogEnd, 0.f));
+    }
     if (!converged || floor_hit || failed) off2 = offnorm2();
     const int fin = (int)(g & 1);
     for (int x = tid; x < n; x += kJThreads) lam_u[S.phys(x)] = failed ? (double)NAN : dg[fin][x];
@@ -526,7 +576,7 @@ __global__ __launch_bounds__(kJThreads) void jacobi_kernel(const float *__restri
                                                            double *__restrict__ lam_u, float2 *__restrict__ rlog,
                                                            pca_info *__restrict__ info)
 {
-    jacobi_body<L>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info);
+    jacobi_body<L, false>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info);
 }
 
 constexpr int kReplayThreads = 512;
@@ -609,12 +659,110 @@ __global__ __launch_bounds__(kReplayThreads) void vreplay_kernel(int n, int rows
     vreplay_body(n, rows, rlog, info, VuT, (int)blockIdx.x);
 }
 
+constexpr int kFollowMaxRows = 32;
+constexpr int kFollowSpins = 1 << 19;   // polls of about 1 us on one entry before giving up
+
+// Rows of E replayed beside the Jacobi workgroup (workgroup wg + 1 of the
+// launch): rows r0 .. r0+rows-1, in slot coordinates, double-buffered in the
+// LDS the Jacobi workgroup uses for its matrix; the log is read kLogBatch
+// steps at a time.
+__device__ __forceinline__ void follow_body(int n, int rows, const float2 *__restrict__ rlog,
+                                            float *__restrict__ VuT, int wg)
+{
+    float *vb = reinterpret_cast<float *>(jac_blk);                     // [2][kFollowMaxRows][256]
+    float2 *lcs = reinterpret_cast<float2 *>(vb + 2 * kFollowMaxRows * 256);   // [kLogBatch][kMaxP]
+    __shared__ int st_fail, st_steps;
+    Slots S;
+    S.init(n, nullptr, nullptr);
+    const int P = S.P;
+    const int tid = threadIdx.x;
+    const int r0 = wg * rows;
+    const int tasks = rows * P;
+
+    for (int t = tid; t < rows * n; t += kJThreads) {
+        const int r = t / n, x = t - (t / n) * n;
+        vb[r * 256 + x] = (S.phys(x) == r0 + r) ? 1.f : 0.f;
+    }
+    if (tid == 0) st_fail = 0;
+    __syncthreads();
+    int64_t done_steps = 0;
+    int fail = 0;
+    while (true) {
+        // Wait for every entry of the batch (bounded), then count its steps
+        // before the first end mark.
+        int bad = 0;
+        for (int t = tid; t < kLogBatch * P; t += kJThreads) {
+            const float2 *src = &rlog[done_steps * P + t];
+            float2 e = log_load(src);
+            int spins = 0;
+            while (__float_as_uint(e.x) == 0u && __float_as_uint(e.y) == 0u) {
+                if (++spins > kFollowSpins) { bad = 1; break; }
+                __builtin_amdgcn_s_sleep(32);
+                e = log_load(src);
+            }
+            lcs[t] = e;
+        }
+        if (bad) atomicOr(&st_fail, 1);
+        if (tid == 0) st_steps = kLogBatch;
+        __syncthreads();
+        if (tid < kLogBatch && lcs[tid * P].x == kLogEnd) atomicMin(&st_steps, tid);
+        __syncthreads();
+        fail = st_fail;
+        const int nb = st_steps;
+        if (fail) break;
+        for (int gg = 0; gg < nb; ++gg) {
+            const int vin = (int)((done_steps + gg) & 1);
+            const float *src = vb + vin * (kFollowMaxRows * 256);
+            float *dst = vb + (vin ^ 1) * (kFollowMaxRows * 256);
+            for (int t = tid; t < tasks; t += kJThreads) {
+                const int r = t / P, k = t - (t / P) * P;
+                const float2 cs = lcs[gg * P + k];
+                const float vT = src[r * 256 + k], vB = src[r * 256 + P + k];
+                dst[r * 256 + S.next(k)] = cs.x * vT - cs.y * vB;
+                dst[r * 256 + S.next(P + k)] = cs.y * vT + cs.x * vB;
+            }
+            __syncthreads();
+        }
+        done_steps += nb;
+        if (nb < kLogBatch) break;
+        __syncthreads();   // lcs is rewritten by the next batch
+    }
+    const float *fin = vb + (int)(done_steps & 1) * (kFollowMaxRows * 256);
+    for (int t = tid; t < rows * n; t += kJThreads) {
+        const int r = t / n, x = t - (t / n) * n;
+        if (r0 + r < n) VuT[(int64_t)S.phys(x) * n + r0 + r] = fail ? (float)NAN : fin[r * 256 + x];
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(kJThreads) void jacobi_follow_kernel(const float *__restrict__ C, int m, int n,
+                                                                  double tol, int max_sweeps, int fp64_angles,
+                                                                  double *__restrict__ lam_u,
+                                                                  float2 *__restrict__ rlog,
+                                                                  pca_info *__restrict__ info, int rows,
+                                                                  float *__restrict__ VuT)
+{
+    if (blockIdx.x == 0)
+        jacobi_body<L, true>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info);
+    else
+        follow_body(n, rows, rlog, VuT, (int)blockIdx.x - 1);
+}
+
 // One wave per output column: rank by counting (stable, descending), then the
 // sign from the column's largest-magnitude entry (lowest row on ties).
 __device__ __forceinline__ void sort_sign_body(int m, int n, const double *__restrict__ lam_u, const float *__restrict__ VuT,
                                       const pca_info *__restrict__ info_ws, float *__restrict__ eigvals,
-                                      float *__restrict__ V, pca_info *__restrict__ info_out, int wg)
+                                      float *__restrict__ V, pca_info *__restrict__ info_out, int wg,
+                                      float2 *__restrict__ rlog_clear)
 {
+    // The launches that read the rotation log have ended: zero its used
+    // batches for the next call that reads it while it is written.
+    if (rlog_clear) {
+        const int64_t T = info_ws->steps;
+        const int64_t used = (T / kLogBatch + 1) * kLogBatch * (n / 2);
+        for (int64_t t = (int64_t)wg * blockDim.x + threadIdx.x; t < used; t += (int64_t)gridDim.x * blockDim.x)
+            rlog_clear[t] = make_float2(0.f, 0.f);
+    }
     __shared__ int perm[256];
     __shared__ double lam[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -671,9 +819,10 @@ __global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const doub
                                                         const float *__restrict__ VuT,
                                                         const pca_info *__restrict__ info_ws,
                                                         float *__restrict__ eigvals, float *__restrict__ V,
-                                                        pca_info *__restrict__ info_out)
+                                                        pca_info *__restrict__ info_out,
+                                                        float2 *__restrict__ rlog_clear)
 {
-    sort_sign_body(m, n, lam_u, VuT, info_ws, eigvals, V, info_out, (int)blockIdx.x);
+    sort_sign_body(m, n, lam_u, VuT, info_ws, eigvals, V, info_out, (int)blockIdx.x, rlog_clear);
 }
 
 // ---- batched form ------------------------------------------------------------
@@ -701,7 +850,8 @@ __global__ __launch_bounds__(kJThreads) void jacobi_batched_kernel(const char *w
                                                                    int fp64_angles)
 {
     const BatchCube &cb = jbatch_table(ws)[blockIdx.x];
-    jacobi_body<kBatchL>(cb.C, cb.m, cb.m + (cb.m & 1), tol, max_sweeps, fp64_angles, cb.lam_u, cb.rlog, cb.info_ws);
+    jacobi_body<kBatchL, false>(cb.C, cb.m, cb.m + (cb.m & 1), tol, max_sweeps, fp64_angles, cb.lam_u, cb.rlog,
+                                cb.info_ws);
 }
 
 __global__ __launch_bounds__(kReplayThreads) void vreplay_batched_kernel(const char *ws, int nc)
@@ -718,15 +868,29 @@ __global__ __launch_bounds__(256) void sort_sign_batched_kernel(const char *ws, 
     const int64_t item = blockIdx.x;
     const BatchCube &cb = t[jbatch_find<&BatchCube::w_sort>(t, nc, item)];
     sort_sign_body(cb.m, cb.m + (cb.m & 1), cb.lam_u, cb.Vu, cb.info_ws, cb.eigvals, cb.V, cb.info,
-                   (int)(item - cb.w_sort));
+                   (int)(item - cb.w_sort), nullptr);
+}
+
+// Rows of E per follower workgroup: about two replay tasks per thread.
+int follow_rows(int P)
+{
+    int r = 2 * kJThreads / P;
+    return r < 1 ? 1 : (r > kFollowMaxRows ? kFollowMaxRows : r);
 }
 
 template <int L>
 void launch_jac(const float *C, int m, int n, double tol, int max_sweeps, int fp64_angles, double *lam_u,
-                float2 *rlog, pca_info *info_ws, hipStream_t st)
+                float2 *rlog, pca_info *info_ws, int overlap, float *Vu, hipStream_t st)
 {
-    hipLaunchKernelGGL(jacobi_kernel<L>, dim3(1), dim3(kJThreads), 0, st, C, m, n, tol, max_sweeps, fp64_angles,
-                       lam_u, rlog, info_ws);
+    if (overlap) {
+        const int rows = follow_rows(n / 2);
+        const unsigned nf = (unsigned)((n + rows - 1) / rows);
+        hipLaunchKernelGGL(jacobi_follow_kernel<L>, dim3(1 + nf), dim3(kJThreads), 0, st, C, m, n, tol, max_sweeps,
+                           fp64_angles, lam_u, rlog, info_ws, rows, Vu);
+    } else {
+        hipLaunchKernelGGL(jacobi_kernel<L>, dim3(1), dim3(kJThreads), 0, st, C, m, n, tol, max_sweeps, fp64_angles,
+                           lam_u, rlog, info_ws);
+    }
 }
 
 // Generic segments of length at most L for P pairs.
@@ -739,9 +903,9 @@ int jac_segments(int P, int L)
 
 }  // namespace
 
-hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int fp64_angles, const JacPlan &plan,
-                         double *lam_u, float2 *rlog, float *Vu, pca_info *info_ws, float *eigvals, float *V,
-                         pca_info *info_out, hipStream_t st)
+hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int fp64_angles, int overlap,
+                         const JacPlan &plan, double *lam_u, float2 *rlog, float *Vu, pca_info *info_ws,
+                         float *eigvals, float *V, pca_info *info_out, hipStream_t st)
 {
     const int n = plan.me;
     const int P = plan.npairs;
@@ -751,18 +915,21 @@ hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int 
     int L = 1;
     while (L < kBatchL && jac_segments(P, L) > kJThreads) L += 2;
     switch (L) {
-    case 1: launch_jac<1>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    case 3: launch_jac<3>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    case 5: launch_jac<5>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    case 7: launch_jac<7>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
-    default: launch_jac<kBatchL>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, st); break;
+    case 1: launch_jac<1>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, overlap, Vu, st); break;
+    case 3: launch_jac<3>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, overlap, Vu, st); break;
+    case 5: launch_jac<5>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, overlap, Vu, st); break;
+    case 7: launch_jac<7>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, overlap, Vu, st); break;
+    default: launch_jac<kBatchL>(C, m, n, tol, max_sweeps, fp64_angles, lam_u, rlog, info_ws, overlap, Vu, st); break;
     }
-    const int rows = replay_rows(n);
-    const unsigned nwg = (unsigned)((n + rows - 1) / rows);
-    hipLaunchKernelGGL(vreplay_kernel, dim3(nwg), dim3(kReplayThreads), 0, st, n, rows, rlog,
-                       (const pca_info *)info_ws, Vu);
+    if (!overlap) {
+        const int rows = replay_rows(n);
+        const unsigned nwg = (unsigned)((n + rows - 1) / rows);
+        hipLaunchKernelGGL(vreplay_kernel, dim3(nwg), dim3(kReplayThreads), 0, st, n, rows, rlog,
+                           (const pca_info *)info_ws, Vu);
+    }
     hipLaunchKernelGGL(sort_sign_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, m, n,
-                       (const double *)lam_u, (const float *)Vu, (const pca_info *)info_ws, eigvals, V, info_out);
+                       (const double *)lam_u, (const float *)Vu, (const pca_info *)info_ws, eigvals, V, info_out,
+                       rlog);
     return hipGetLastError();
 }
 

@@ -73,13 +73,18 @@ struct JacPlan {
     size_t bytes_vu;     // unsorted eigenvectors, float32 me x me
     size_t bytes_info;   // internal pca_info
 };
+
+// The rotation log is read in batches of kLogBatch steps while it is written
+// (overlapped replay); its capacity covers the batch that holds the step
+// after the last one.
+constexpr int kLogBatch = 16;
 __host__ __device__ inline JacPlan jac_plan(int m, int max_sweeps)
 {
     JacPlan p;
     p.me = m + (m & 1);
     p.npairs = p.me / 2;
-    p.log_steps = (int64_t)(max_sweeps > 0 ? max_sweeps : 0) * (p.me - 1);
-    p.bytes_log = (size_t)(p.log_steps > 0 ? p.log_steps : 1) * p.npairs * 2 * sizeof(float);
+    p.log_steps = ((int64_t)(max_sweeps > 0 ? max_sweeps : 0) * (p.me - 1) / kLogBatch + 1) * kLogBatch;
+    p.bytes_log = (size_t)p.log_steps * p.npairs * 2 * sizeof(float);
     p.bytes_lam = (size_t)p.me * sizeof(double);
     p.bytes_vu = (size_t)p.me * p.me * sizeof(float);
     p.bytes_info = sizeof(pca_info);
@@ -181,7 +186,10 @@ hipError_t launch_backward(const float *Y, int64_t n, int m, int64_t ld, const f
                            float *dY, int64_t ldd, const BwdPlan &p, double *part, double *wbuf, double *sums,
                            float *G, hipStream_t st);
 
-hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int fp64_angles,
+// overlap = 1: the eigenvector replay runs in the Jacobi launch itself, on
+// workgroups that follow the rotation log as it is written (the log must
+// start zeroed; every call leaves it zeroed).
+hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int fp64_angles, int overlap,
                          const JacPlan &plan, double *lam_u, float2 *log, float *Vu,
                          pca_info *info_ws, float *eigvals, float *V, pca_info *info_out,
                          hipStream_t st);
