@@ -1,14 +1,21 @@
 // Projection of every pixel onto the first k eigenvectors (Algorithm 1, lines
 // 5-6): Q'[p, i] = sum_b (Y[p, b] - mu_b) V[b, i], i < k.
 //
-// Persistent workgroups (two per CU) walk over tiles of 64 pixels. A tile is
-// read from HBM with coalesced row loads, centred on the way into LDS (the
-// centred cube is never written back), and multiplied by the block
-// V[:, 16g .. 16g+15] with v_mfma_f32_16x16x4_f32 (K = bands), each wave
-// taking 16 pixels. The eigenvector block stays in registers for the
-// workgroup's lifetime, and the next tile's loads are in flight while the
-// current tile is multiplied. The cube is read once per group of 16
-// components (once for k <= 16).
+// Persistent workgroups walk over tiles of pixels. A tile is read from HBM
+// with coalesced row loads, centred on the way into LDS (the centred cube is
+// never written back), and multiplied by the block V[:, 16g .. 16g+15] with
+// v_mfma_f32_16x16x4_f32 (K = bands). The eigenvector block stays in
+// registers for the workgroup's lifetime. The cube is read once per group of
+// 16 components (once for k <= 16).
+//
+// project_kernel (one cube): tiles of 32 pixels, three workgroups per CU, and
+// the loads of the next two tiles of a workgroup in flight while it stages
+// and multiplies the current one, so that enough of the cube is in flight to
+// keep HBM busy (the eigenvector block sits in LDS to leave the registers to
+// those tiles). Waves 0/1 multiply pixels 0-15/16-31 over the first half of
+// the bands, waves 2/3 over the second half; the halves are added through
+// LDS. The batched form uses 64-pixel tiles (each wave 16 pixels, all bands,
+// the eigenvector block in registers) with one tile in flight.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "loader.hpp"
@@ -20,7 +27,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTP = 64;                  // pixels per tile (4 waves x 16)
 constexpr int kMaxKSteps = 64;           // 256 bands / 4
-constexpr int kWGPerCU = 2;
 
 // Tile pitch (floats): a multiple of 4 with pitch/4 odd, so the 16 pixels x 4
 // bands read by one MFMA operand load hit 64 distinct LDS banks.
@@ -119,14 +125,114 @@ __device__ __forceinline__ void project_body(const T *__restrict__ Y, int64_t n,
     }
 }
 
+constexpr int kTS = 32;          // pixels per tile of project_kernel (4 waves x 8 rows)
+constexpr int kWGPerCUS = 3;       // LDS: 3 x 52.7 KB
+constexpr int kMaxHalf = 32;     // K steps per half of the bands (256 / 4 / 2)
+
 template <typename T, int VEC>
-__global__ __launch_bounds__(kThreads) void project_kernel(const T *__restrict__ Y, int64_t n, int m,
+__device__ __forceinline__ void project_stream_body(const T *__restrict__ Y, int64_t n, int m, int64_t ld,
+                                                    const float *__restrict__ mean, const float *__restrict__ V,
+                                                    int k, float *__restrict__ Q, int64_t t0, int64_t tstep,
+                                                    int64_t ntiles, int g)
+{
+    __shared__ __attribute__((aligned(16))) float tile[kTS * 260];
+    __shared__ float mu[256];
+    __shared__ f32x4 red[2][64];
+    __shared__ float vsh[kMaxKSteps][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m4 = round_up(m, 4);
+    const int pitch = proj_pitch(m4);
+    const int ksteps = m4 / 4;
+    const int half = (ksteps + 1) / 2;
+    const int gq = wave & 1, h = wave >> 1;
+    const int s0 = h * half;
+    const int ns = min(half, ksteps - s0);
+
+    for (int b = tid; b < 256; b += kThreads) mu[b] = (mean && b < m) ? mean[b] : 0.f;
+
+    // B operand of K step s, lane l: V[4 s + l/16][16g + l%16], kept in LDS
+    // (read once per product; registers go to the tiles in flight).
+    for (int e = tid; e < ksteps * 64; e += kThreads) {
+        const int sk = e >> 6, l = e & 63;
+        const int b = 4 * sk + (l >> 4), o = 16 * g + (l & 15);
+        vsh[sk][l] = (b < m && o < k) ? V[(int64_t)b * m + o] : 0.f;
+    }
+    __syncthreads();
+    const float *bcol = &vsh[s0][lane];
+
+    const float *arow = &tile[(16 * gq + (lane & 15)) * pitch + 4 * s0 + (lane >> 4)];
+    // One tile: stage (centre into LDS), refill the group's registers with the
+    // tile two steps ahead, multiply, add the band halves, store.
+    auto step = [&](Group<T, VEC> &v, int64_t t) {
+        const int64_t pg = t * kTS + 8 * wave;
+        if constexpr (VEC == 4) {
+            const int b = 4 * lane;
+            if (b < m4) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    f32x4 q;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) q[s] = (b + s < m && pg + i < n) ? v.get(i, s) - mu[b + s] : 0.f;
+                    *reinterpret_cast<f32x4 *>(&tile[(8 * wave + i) * pitch + b]) = q;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int b = lane + 64 * s;
+                if (b < m4) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        tile[(8 * wave + i) * pitch + b] = (b < m && pg + i < n) ? v.get(i, s) - mu[b] : 0.f;
+                }
+            }
+        }
+        __syncthreads();
+        const int64_t tn = t + 2 * tstep;
+        if (tn < ntiles) v.load(Y, ld, tn * kTS + 8 * wave, n, m, lane);
+
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < kMaxHalf; ++s) {
+            if (s < ns) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[4 * s], bcol[64 * s], acc, 0, 0, 0);
+        }
+        if (h == 1) red[gq][lane] = acc;
+        __syncthreads();
+        if (h == 0) {
+            acc += red[gq][lane];
+            // 16x16 result layout: lane holds rows 4 (lane/16) + r, column lane % 16.
+            const int o = 16 * g + (lane & 15);
+            if (o < k) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t p = t * kTS + 16 * gq + 4 * (lane >> 4) + r;
+                    if (p < n) Q[p * k + o] = acc[r];
+                }
+            }
+        }
+    };
+
+    Group<T, VEC> va, vb;
+    int64_t t = t0;
+    if (t < ntiles) va.load(Y, ld, t * kTS + 8 * wave, n, m, lane);
+    if (t + tstep < ntiles) vb.load(Y, ld, (t + tstep) * kTS + 8 * wave, n, m, lane);
+    while (t < ntiles) {
+        step(va, t);
+        t += tstep;
+        if (t >= ntiles) break;
+        step(vb, t);
+        t += tstep;
+    }
+}
+
+template <typename T, int VEC>
+__global__ __launch_bounds__(kThreads, kWGPerCUS) void project_kernel(const T *__restrict__ Y, int64_t n, int m,
                                                            int64_t ld, const float *__restrict__ mean,
                                                            const float *__restrict__ V, int k,
                                                            float *__restrict__ Q)
 {
-    project_body<T, VEC>(Y, n, m, ld, mean, V, k, Q, (int64_t)blockIdx.x, (int64_t)gridDim.x, (n + kTP - 1) / kTP,
-                         (int)blockIdx.y);
+    project_stream_body<T, VEC>(Y, n, m, ld, mean, V, k, Q, (int64_t)blockIdx.x, (int64_t)gridDim.x,
+                                (n + kTS - 1) / kTS, (int)blockIdx.y);
 }
 
 // Batched: one work item = a run of tiles of one cube; blockIdx.y = the
@@ -167,8 +273,8 @@ template <typename T>
 hipError_t launch_t(const T *Y, int64_t n, int m, int64_t ld, const float *mean, const float *V, int k,
                     float *Q, hipStream_t st, bool v4)
 {
-    const int64_t ntiles = (n + kTP - 1) / kTP;
-    int64_t gx = (int64_t)num_cus() * kWGPerCU;
+    const int64_t ntiles = (n + kTS - 1) / kTS;
+    int64_t gx = (int64_t)num_cus() * kWGPerCUS;
     if (gx > ntiles) gx = ntiles;
     dim3 grid((unsigned)gx, (unsigned)((k + 15) / 16)), block(kThreads);
     if (v4)
