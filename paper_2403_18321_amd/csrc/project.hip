@@ -4,18 +4,17 @@
 // Persistent workgroups walk over tiles of pixels. A tile is read from HBM
 // with coalesced row loads, centred on the way into LDS (the centred cube is
 // never written back), and multiplied by the block V[:, 16g .. 16g+15] with
-// v_mfma_f32_16x16x4_f32 (K = bands). The eigenvector block stays in
-// registers for the workgroup's lifetime. The cube is read once per group of
-// 16 components (once for k <= 16).
+// v_mfma_f32_16x16x4_f32 (K = bands). The eigenvector block stays in LDS for
+// the workgroup's lifetime, which leaves the registers to the tiles in
+// flight. The cube is read once per group of 16 components (once for k <= 16).
 //
-// project_kernel (one cube): tiles of 32 pixels, three workgroups per CU, and
-// the loads of the next two tiles of a workgroup in flight while it stages
-// and multiplies the current one, so that enough of the cube is in flight to
-// keep HBM busy (the eigenvector block sits in LDS to leave the registers to
-// those tiles). Waves 0/1 multiply pixels 0-15/16-31 over the first half of
-// the bands, waves 2/3 over the second half; the halves are added through
-// LDS. The batched form uses 64-pixel tiles (each wave 16 pixels, all bands,
-// the eigenvector block in registers) with one tile in flight.
+// Tiles of 32 pixels, three workgroups per CU, and the loads of the next two
+// tiles of a workgroup in flight while it stages and multiplies the current
+// one, so that enough of the cube is in flight to keep HBM busy. Waves 0/1
+// multiply pixels 0-15/16-31 over the first half of the bands, waves 2/3 over
+// the second half; the halves are added through LDS. project_kernel walks the
+// tiles of one cube; project_batched_kernel runs the same body over runs of
+// tiles of the cubes of a batch.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "loader.hpp"
@@ -25,105 +24,12 @@ namespace pca {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kTP = 64;                  // pixels per tile (4 waves x 16)
+constexpr int kTP = 64;                  // pixels per batched work-item tile unit (kProjTile)
 constexpr int kMaxKSteps = 64;           // 256 bands / 4
 
 // Tile pitch (floats): a multiple of 4 with pitch/4 odd, so the 16 pixels x 4
 // bands read by one MFMA operand load hit 64 distinct LDS banks.
 __host__ __device__ inline int proj_pitch(int m4) { return ((m4 / 4) & 1) ? m4 : m4 + 4; }
-
-// Tiles t0, t0 + tstep, ... (< tend) of one cube, component group g.
-template <typename T, int VEC>
-__device__ __forceinline__ void project_body(const T *__restrict__ Y, int64_t n, int m, int64_t ld,
-                                    const float *__restrict__ mean, const float *__restrict__ V, int k,
-                                    float *__restrict__ Q, int64_t t0, int64_t tstep, int64_t tend, int g)
-{
-    __shared__ __attribute__((aligned(16))) float tile[kTP * 260];
-    __shared__ float mu[256];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m4 = round_up(m, 4);
-    const int pitch = proj_pitch(m4);
-    const int ksteps = m4 / 4;
-    const int64_t ntiles = tend;
-
-    for (int b = tid; b < 256; b += kThreads) mu[b] = (mean && b < m) ? mean[b] : 0.f;
-
-    // B operand: lane holds V[4s + lane/16][16g + lane%16] for every K step s.
-    float bv[kMaxKSteps];
-    {
-        const int o = 16 * g + (lane & 15);
-#pragma unroll
-        for (int s = 0; s < kMaxKSteps; ++s) {
-            const int b = 4 * s + (lane >> 4);
-            bv[s] = (s < ksteps && b < m && o < k) ? V[(int64_t)b * m + o] : 0.f;
-        }
-    }
-    __syncthreads();
-
-    // Wave w loads pixel groups w and w + 4 (8 pixels each) of a tile.
-    Group<T, VEC> v0, v1;
-    int64_t t = t0;
-    if (t < ntiles) {
-        v0.load(Y, ld, t * kTP + 8 * wave, n, m, lane);
-        v1.load(Y, ld, t * kTP + 8 * (wave + 4), n, m, lane);
-    }
-    const float *arow = &tile[(16 * wave + (lane & 15)) * pitch + (lane >> 4)];
-    for (; t < ntiles; t += tstep) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int grp = wave + 4 * h;
-            const Group<T, VEC> &v = h == 0 ? v0 : v1;
-            const int64_t pg = t * kTP + 8 * grp;
-            if constexpr (VEC == 4) {
-                const int b = 4 * lane;
-                if (b < m4) {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        f32x4 q;
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) q[s] = (b + s < m && pg + i < n) ? v.get(i, s) - mu[b + s] : 0.f;
-                        *reinterpret_cast<f32x4 *>(&tile[(8 * grp + i) * pitch + b]) = q;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int b = lane + 64 * s;
-                    if (b < m4) {
-#pragma unroll
-                        for (int i = 0; i < 8; ++i)
-                            tile[(8 * grp + i) * pitch + b] = (b < m && pg + i < n) ? v.get(i, s) - mu[b] : 0.f;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-
-        // Next tile's loads overlap this tile's products.
-        const int64_t tn = t + tstep;
-        if (tn < ntiles) {
-            v0.load(Y, ld, tn * kTP + 8 * wave, n, m, lane);
-            v1.load(Y, ld, tn * kTP + 8 * (wave + 4), n, m, lane);
-        }
-
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < kMaxKSteps; ++s) {
-            if (s < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[4 * s], bv[s], acc, 0, 0, 0);
-        }
-
-        // 16x16 result layout: lane holds rows 4 (lane/16) + r, column lane % 16.
-        const int o = 16 * g + (lane & 15);
-        if (o < k) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t p = t * kTP + 16 * wave + 4 * (lane >> 4) + r;
-                if (p < n) Q[p * k + o] = acc[r];
-            }
-        }
-        __syncthreads();
-    }
-}
 
 constexpr int kTS = 32;          // pixels per tile of project_kernel (4 waves x 8 rows)
 constexpr int kWGPerCUS = 3;       // LDS: 3 x 52.7 KB
@@ -238,7 +144,7 @@ __global__ __launch_bounds__(kThreads, kWGPerCUS) void project_kernel(const T *_
 // Batched: one work item = a run of tiles of one cube; blockIdx.y = the
 // 16-component group (workgroups beyond a cube's k return at once).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void project_batched_kernel(const char *ws, int nc)
+__global__ __launch_bounds__(kThreads, kWGPerCUS) void project_batched_kernel(const char *ws, int nc)
 {
     const BatchCube *t = reinterpret_cast<const BatchCube *>(ws + sizeof(BatchHeader));
     const int64_t item = blockIdx.x;
@@ -251,10 +157,13 @@ __global__ __launch_bounds__(kThreads) void project_batched_kernel(const char *w
     const BatchCube &cb = t[lo];
     const int g = blockIdx.y;
     if (16 * g >= cb.k) return;
-    const int64_t ntiles = (cb.n + kTP - 1) / kTP;
-    const int64_t t0 = (item - cb.w_proj) * cb.proj_tiles;
-    const int64_t t1 = (t0 + cb.proj_tiles < ntiles) ? t0 + cb.proj_tiles : ntiles;
-    project_body<T, 1>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, cb.mean, cb.V, cb.k, cb.Q, t0, 1, t1, g);
+    // A work item is proj_tiles 64-pixel tiles, i.e. twice as many 32-pixel ones.
+    const int64_t ntiles = (cb.n + kTS - 1) / kTS;
+    const int64_t per = (int64_t)cb.proj_tiles * (kTP / kTS);
+    const int64_t t0 = (item - cb.w_proj) * per;
+    const int64_t t1 = (t0 + per < ntiles) ? t0 + per : ntiles;
+    project_stream_body<T, 1>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, cb.mean, cb.V, cb.k, cb.Q, t0, 1, t1,
+                              g);
 }
 
 int num_cus()
