@@ -63,8 +63,9 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 }
 
 // One chunk c of one cube (the body of the single-cube and the batched
-// launches).
-template <typename T, int VEC, int MODE, int S>
+// launches). kSkip: products of slots past the cube's last block are skipped
+// (the batched launch sizes S for the widest cube of any batch).
+template <typename T, int VEC, int MODE, int S, bool kSkip = false>
 __device__ __forceinline__ void cov_partial_body(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
     int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
@@ -201,14 +202,17 @@ __device__ __forceinline__ void cov_partial_body(
             for (int kk = 0; kk < KT / 2; ++kk) {
                 const float *tr = tileF + (2 * kk + (lane >> 5)) * pf;
 #pragma unroll
-                for (int e = 0; e < S; ++e)
+                for (int e = 0; e < S; ++e) {
+                    if (kSkip && 4 * e + wave >= nbl) continue;
                     acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(tr[offI[e]], tr[offJ[e]], acc[e], 0, 0, 0);
+                }
             }
         } else {
 #pragma unroll
             for (int kk = 0; kk < KT / 16; ++kk) {
 #pragma unroll
                 for (int e = 0; e < S; ++e) {
+                    if (kSkip && 4 * e + wave >= nbl) continue;
                     const bf16x8 hi_i = *reinterpret_cast<const bf16x8 *>(&hiT[offI[e] + 16 * kk]);
                     const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&loT[offI[e] + 16 * kk]);
                     const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hiT[offJ[e] + 16 * kk]);
@@ -894,9 +898,9 @@ __global__ __launch_bounds__(kThreads) void cov_partial_batched_kernel(char *ws,
         const int64_t item = item_sh;
         if (item >= total) break;
         const BatchCube &cb = t[batch_find<&BatchCube::w_cov>(t, nc, item)];
-        cov_partial_body<T, 1, MODE, kMaxSlots>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, 0, cb.cov.chunk,
-                                                cb.cov.nb, cb.cov.nblk, cb.cov.mpad, cb.partS, cb.partSum,
-                                                cb.partShift, item - cb.w_cov);
+        cov_partial_body<T, 1, MODE, kMaxSlots, true>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, 0,
+                                                      cb.cov.chunk, cb.cov.nb, cb.cov.nblk, cb.cov.mpad, cb.partS,
+                                                      cb.partSum, cb.partShift, item - cb.w_cov);
     }
 }
 
