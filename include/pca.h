@@ -252,9 +252,11 @@ pca_status pca_batched_workspace_size(const pca_cube *cubes, int32_t n_cubes, in
  * compute it alone, in eight launches for the whole batch: a set-up kernel
  * that builds the task table in the workspace, one persistent covariance
  * launch whose workgroups take (cube, pixel chunk) items from a queue,
- * largest band counts first, the float64 chunk combination, one Jacobi
- * launch with a workgroup per cube (each cube's rotations on its own CU),
- * the eigenvector replay, the sort and sign fix, and one projection launch.
+ * largest band counts first, the float64 chunk combination, a launch that
+ * zeroes the rotation logs, one Jacobi launch with a workgroup per cube (each
+ * cube's rotations on its own CU) followed by workgroups that form the
+ * eigenvectors from those logs while the sweeps run, the sort and sign fix,
+ * and one projection launch.
  *   cubes      host array of n_cubes descriptors (validation and sizing).
  *   cubes_dev  the same array in device memory (read by the set-up kernel;
  *              keeping it resident makes the sequence capturable in a graph).

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kSetupThreads) void batch_setup_kernel(const pca_cu
         c.info_ws = reinterpret_cast<pca_info *>(a);
         a += batch_al(jp.bytes_info);
         area += batch_cube_bytes(c.cov, jp, c.m);
-        c.rows = replay_rows(jp.me);
+        c.rows = follow_rows(jp.me);
         c.proj_tiles = proj_tiles;
         int64_t cnt[6];
         batch_counts(c.cov, c.n, c.m, proj_tiles, cnt);

@@ -659,7 +659,6 @@ __global__ __launch_bounds__(kReplayThreads) void vreplay_kernel(int n, int rows
     vreplay_body(n, rows, rlog, info, VuT, (int)blockIdx.x);
 }
 
-constexpr int kFollowMaxRows = 32;
 constexpr int kFollowSpins = 1 << 19;   // polls of about 1 us on one entry before giving up
 
 // Rows of E replayed beside the Jacobi workgroup (workgroup wg + 1 of the
@@ -752,7 +751,7 @@ __global__ __launch_bounds__(kJThreads) void jacobi_follow_kernel(const float *_
 // sign from the column's largest-magnitude entry (lowest row on ties).
 __device__ __forceinline__ void sort_sign_body(int m, int n, const double *__restrict__ lam_u, const float *__restrict__ VuT,
                                       const pca_info *__restrict__ info_ws, float *__restrict__ eigvals,
-                                      float *__restrict__ V, pca_info *__restrict__ info_out, int wg,
+                                      float *__restrict__ V, pca_info *__restrict__ info_out, int wg, int nwg,
                                       float2 *__restrict__ rlog_clear)
 {
     // The launches that read the rotation log have ended: zero its used
@@ -760,7 +759,7 @@ __device__ __forceinline__ void sort_sign_body(int m, int n, const double *__res
     if (rlog_clear) {
         const int64_t T = info_ws->steps;
         const int64_t used = (T / kLogBatch + 1) * kLogBatch * (n / 2);
-        for (int64_t t = (int64_t)wg * blockDim.x + threadIdx.x; t < used; t += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t t = (int64_t)wg * blockDim.x + threadIdx.x; t < used; t += (int64_t)nwg * blockDim.x)
             rlog_clear[t] = make_float2(0.f, 0.f);
     }
     __shared__ int perm[256];
@@ -822,7 +821,7 @@ __global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const doub
                                                         pca_info *__restrict__ info_out,
                                                         float2 *__restrict__ rlog_clear)
 {
-    sort_sign_body(m, n, lam_u, VuT, info_ws, eigvals, V, info_out, (int)blockIdx.x, rlog_clear);
+    sort_sign_body(m, n, lam_u, VuT, info_ws, eigvals, V, info_out, (int)blockIdx.x, (int)gridDim.x, rlog_clear);
 }
 
 // ---- batched form ------------------------------------------------------------
@@ -845,21 +844,40 @@ __device__ inline int jbatch_find(const BatchCube *t, int nc, int64_t item)
     return lo;
 }
 
-// One workgroup (one CU) per cube.
-__global__ __launch_bounds__(kJThreads) void jacobi_batched_kernel(const char *ws, double tol, int max_sweeps,
-                                                                   int fp64_angles)
-{
-    const BatchCube &cb = jbatch_table(ws)[blockIdx.x];
-    jacobi_body<kBatchL, false>(cb.C, cb.m, cb.m + (cb.m & 1), tol, max_sweeps, fp64_angles, cb.lam_u, cb.rlog,
-                                cb.info_ws);
-}
-
-__global__ __launch_bounds__(kReplayThreads) void vreplay_batched_kernel(const char *ws, int nc)
+// Zeroes every cube's whole rotation log before the batched Jacobi launch
+// (the followers read the logs while they are written, and a batch's
+// workspace layout, so where each log sits, changes with the batch and the
+// tile sizes; no state is carried from call to call).
+__global__ __launch_bounds__(256) void log_clear_batched_kernel(const char *ws, int nc, int max_sweeps)
 {
     const BatchCube *t = jbatch_table(ws);
-    const int64_t item = blockIdx.x;
-    const BatchCube &cb = t[jbatch_find<&BatchCube::w_rep>(t, nc, item)];
-    vreplay_body(cb.m + (cb.m & 1), cb.rows, cb.rlog, cb.info_ws, cb.Vu, (int)(item - cb.w_rep));
+    for (int c = 0; c < nc; ++c) {
+        const BatchCube &cb = t[c];
+        const JacPlan jp = jac_plan(cb.m, max_sweeps);
+        const int64_t n4 = jp.log_steps * jp.npairs / 2;   // two entries per 16 bytes (log_steps is a multiple of 16)
+        float4 *p = reinterpret_cast<float4 *>(cb.rlog);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+            p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// Workgroups 0 .. nc-1: the Jacobi sweeps of cube blockIdx.x (one CU each);
+// the rest: follower workgroups replaying the rotation logs as they are
+// written (cube order, so the widest cubes' followers are dispatched first;
+// followers that find no free CU start later and replay a finished log).
+__global__ __launch_bounds__(kJThreads) void jacobi_batched_kernel(const char *ws, int nc, double tol, int max_sweeps,
+                                                                   int fp64_angles)
+{
+    const BatchCube *t = jbatch_table(ws);
+    if ((int)blockIdx.x < nc) {
+        const BatchCube &cb = t[blockIdx.x];
+        jacobi_body<kBatchL, true>(cb.C, cb.m, cb.m + (cb.m & 1), tol, max_sweeps, fp64_angles, cb.lam_u, cb.rlog,
+                                   cb.info_ws);
+    } else {
+        const int64_t item = (int64_t)blockIdx.x - nc;
+        const BatchCube &cb = t[jbatch_find<&BatchCube::w_rep>(t, nc, item)];
+        follow_body(cb.m + (cb.m & 1), cb.rows, cb.rlog, cb.Vu, (int)(item - cb.w_rep));
+    }
 }
 
 __global__ __launch_bounds__(256) void sort_sign_batched_kernel(const char *ws, int nc)
@@ -868,22 +886,16 @@ __global__ __launch_bounds__(256) void sort_sign_batched_kernel(const char *ws, 
     const int64_t item = blockIdx.x;
     const BatchCube &cb = t[jbatch_find<&BatchCube::w_sort>(t, nc, item)];
     sort_sign_body(cb.m, cb.m + (cb.m & 1), cb.lam_u, cb.Vu, cb.info_ws, cb.eigvals, cb.V, cb.info,
-                   (int)(item - cb.w_sort), nullptr);
+                   (int)(item - cb.w_sort), (cb.m + 3) / 4, nullptr);
 }
 
-// Rows of E per follower workgroup: about two replay tasks per thread.
-int follow_rows(int P)
-{
-    int r = 2 * kJThreads / P;
-    return r < 1 ? 1 : (r > kFollowMaxRows ? kFollowMaxRows : r);
-}
 
 template <int L>
 void launch_jac(const float *C, int m, int n, double tol, int max_sweeps, int fp64_angles, double *lam_u,
                 float2 *rlog, pca_info *info_ws, int overlap, float *Vu, hipStream_t st)
 {
     if (overlap) {
-        const int rows = follow_rows(n / 2);
+        const int rows = follow_rows(n);
         const unsigned nf = (unsigned)((n + rows - 1) / rows);
         hipLaunchKernelGGL(jacobi_follow_kernel<L>, dim3(1 + nf), dim3(kJThreads), 0, st, C, m, n, tol, max_sweeps,
                            fp64_angles, lam_u, rlog, info_ws, rows, Vu);
@@ -936,9 +948,9 @@ hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int 
 hipError_t launch_jacobi_batched(const char *ws, const int64_t total[6], int n_cubes, double tol, int max_sweeps,
                                  int fp64_angles, hipStream_t st)
 {
-    hipLaunchKernelGGL(jacobi_batched_kernel, dim3((unsigned)n_cubes), dim3(kJThreads), 0, st, ws, tol, max_sweeps,
-                       fp64_angles);
-    hipLaunchKernelGGL(vreplay_batched_kernel, dim3((unsigned)total[3]), dim3(kReplayThreads), 0, st, ws, n_cubes);
+    hipLaunchKernelGGL(log_clear_batched_kernel, dim3(1024), dim3(256), 0, st, ws, n_cubes, max_sweeps);
+    hipLaunchKernelGGL(jacobi_batched_kernel, dim3((unsigned)(n_cubes + total[3])), dim3(kJThreads), 0, st, ws,
+                       n_cubes, tol, max_sweeps, fp64_angles);
     hipLaunchKernelGGL(sort_sign_batched_kernel, dim3((unsigned)total[4]), dim3(256), 0, st, ws, n_cubes);
     return hipGetLastError();
 }

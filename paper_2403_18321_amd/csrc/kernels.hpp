@@ -91,11 +91,20 @@ __host__ __device__ inline JacPlan jac_plan(int m, int max_sweeps)
     return p;
 }
 
-// Eigenvector-replay rows per workgroup.
+// Eigenvector-replay rows per workgroup of the separate replay launch.
 __host__ __device__ inline int replay_rows(int me)
 {
     const int r = 512 / (me / 2);
     return r > 8 ? 8 : r;
+}
+
+// Rows of E per follower workgroup (1024 threads) of the overlapped replay:
+// about two replay tasks per thread, at most 32 rows.
+constexpr int kFollowMaxRows = 32;
+__host__ __device__ inline int follow_rows(int me)
+{
+    const int r = 2 * 1024 / (me / 2);
+    return r < 1 ? 1 : (r > kFollowMaxRows ? kFollowMaxRows : r);
 }
 
 // ---- batched form ----------------------------------------------------------
@@ -123,7 +132,7 @@ struct BatchCube {
     double *lam_u;
     float *Vu;
     pca_info *info_ws;
-    int rows;              // eigenvector-replay rows per workgroup
+    int rows;              // eigenvector rows per follower workgroup of the Jacobi launch
     int proj_tiles;        // 64-pixel tiles per projection work item
     // First global work item of this cube in each batched launch.
     int64_t w_cov, w_fin1, w_fin2, w_rep, w_sort, w_proj;
@@ -143,7 +152,7 @@ __host__ __device__ inline void batch_counts(const CovPlan &cp, int64_t n, int m
     w[0] = cp.nchunks;
     w[1] = (int64_t)cp.nblk * cp.groups;
     w[2] = cp.nblk;
-    w[3] = (me + replay_rows(me) - 1) / replay_rows(me);
+    w[3] = (me + follow_rows(me) - 1) / follow_rows(me);
     w[4] = (m + 3) / 4;
     w[5] = ((n + kProjTile - 1) / kProjTile + tiles - 1) / tiles;
 }
