@@ -221,6 +221,67 @@ def bench_batch(P, synth, torch, args):
     return 0
 
 
+def bench_grad(P, synth, torch, args):
+    """The differentiation form: the planted 256x256-pixel, 128-band cube,
+    k = 8, float32; one step = the forward pipeline plus pca_backward for the
+    loss <W, Q> (W a fixed random [pixels, k] array), whose gradient goes
+    through the projection, eigendecomposition, covariance and centring
+    adjoints."""
+    import numpy as np
+    d = synth.make_config("c5")
+    k = d["k"]
+    Yh = d["Y"]
+    n, m = Yh.shape
+    Yd = torch.from_numpy(Yh).cuda()
+    W = (np.random.default_rng(1006).standard_normal((n, k)) / np.sqrt(n)).astype(np.float32)
+    Wd = torch.from_numpy(W).cuda()
+    pipe = P.PCAPipeline(n, m, k, "f32")
+    dY = torch.empty_like(Yd)
+    ws = P.workspace(P.pca_workspace_size(P.PCA_OP_BACKWARD, n, m, k=k))
+
+    def step():
+        pipe.forward(Yd)
+        P.pca_backward(Yd, pipe.mean, pipe.eigvals, pipe.V, k, dY, Wd, None, None, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_fwd = t_bwd = 0.0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    reps = max(3, min(args.steps, 10))
+    for _ in range(reps):
+        ev[0].record(stream)
+        pipe.forward(Yd)
+        ev[1].record(stream)
+        P.pca_backward(Yd, pipe.mean, pipe.eigvals, pipe.V, k, dY, Wd, None, None, ws)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_fwd += ev[0].elapsed_time(ev[1]) / reps
+        t_bwd += ev[1].elapsed_time(ev[2]) / reps
+    out = dict(metric="forward + adjoint PCA Mpixel·band/s", value=round(n * m / (ms * 1e-3) / 1e6, 1),
+               unit="Mpixel·band/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload="planted cube 256x256 px x 128 bands, k=8, loss <W, Q> (forward + pca_backward)",
+                           n_pixels=n, n_bands=m, k=k),
+               stages_ms=dict(forward=round(t_fwd, 4), backward=round(t_bwd, 4)))
+    if not args.no_accuracy:
+        import oracle
+        ref = oracle.backward(Yh.astype(np.float64), k, dQ=W.astype(np.float64))
+        g = dY.cpu().numpy().astype(np.float64)
+        out["grad_rel_err"] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,8 +290,9 @@ def main(argv=None):
     ap.add_argument("--modes", default="f32,bf16x3,bf16x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--workload", choices=("cube224", "batch64"), default="cube224",
-                    help="cube224: the 224-band 1024x1024 cube (the reported line); batch64: the 64-cube batch")
+    ap.add_argument("--workload", choices=("cube224", "batch64", "grad"), default="cube224",
+                    help="cube224: the 224-band 1024x1024 cube (the reported line); batch64: the 64-cube batch; "
+                         "grad: the differentiation form (forward + adjoint)")
     ap.add_argument("--autotune", action="store_true", help="batch64: tune the tile shapes first")
     ap.add_argument("--lanes", type=int, default=1,
                     help="batch64: sub-batches by band count, one pca_batched call and HIP stream each")
@@ -257,6 +319,8 @@ def main(argv=None):
     P.library()  # fail loudly if the HIP library is missing
     if args.workload == "batch64":
         return bench_batch(P, synth, torch, args)
+    if args.workload == "grad":
+        return bench_grad(P, synth, torch, args)
     log("generating the 224-band cube ...")
     d = synth.make_config("c3")
     k = d["k"]
