@@ -19,14 +19,17 @@
 // Kernels, in launch order:
 //   bwd_reduce: per pixel chunk and group of 8 components, float64 sums of
 //               X^T Qbar, 1^T Qbar and 1^T X (X formed on the fly from Y, mu);
-//   bwd_w:      one workgroup per component j: vbar_j (chunk sums in chunk
-//               order plus Vbar_k), u = F[:, j] o (V^T vbar_j), w_j = V u;
+//   bwd_w:      one 1024-thread workgroup per component j: vbar_j (chunk
+//               sums in a fixed order plus Vbar_k), u = F[:, j] o (V^T vbar_j),
+//               w_j = V u;
 //               workgroup 0 also finishes 1^T Qbar and 1^T X;
 //   bwd_g:      G[a][b] = 2/(N-1) sym(Cbar)[a][b] in 16 x 16 tiles;
 //   bwd_r:      rows M .. M+k-1 of G = V_k^T, row M+k = -(1^T Xbar) / N;
 //   bwd_apply:  dY = [X | Qbar | 1] G, one GEMM over all pixels with
 //               v_mfma_f32_32x32x2_f32, 128 pixels per workgroup, the
-//               augmented K dimension staged through LDS 32 at a time.
+//               augmented K dimension staged through LDS 32 at a time (the
+//               next slab's loads in flight during the current one's
+//               products).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -90,51 +93,85 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float *__res
     if (t < kCompGroup) dst[kCompGroup * m + t] = sq;
 }
 
-__global__ __launch_bounds__(kThreads) void bwd_w_kernel(int m, int k, int nchunks, int kg,
-                                                         const double *__restrict__ part,
-                                                         const float *__restrict__ lam,
-                                                         const float *__restrict__ V,
-                                                         const float *__restrict__ dVk,
-                                                         double *__restrict__ wbuf, double *__restrict__ sums)
+constexpr int kWThreads = 1024;     // bwd_w: 4 slices x 256 bands
+constexpr int kWSlices = 4;
+
+// Slice sl of sum_w p[w * stride] over w < count: w = sl, sl + 4, ...,
+// as eight interleaved partial sums added in a fixed order (eight loads in
+// flight).
+__device__ inline double slice_sum(const double *__restrict__ p, int64_t stride, int count, int sl)
 {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int w = sl;
+    for (; w + (8 - 1) * kWSlices < count; w += 8 * kWSlices) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] += p[(int64_t)(w + i * kWSlices) * stride];
+    }
+    for (int i = 0; w < count; w += kWSlices, ++i) a[i] += p[(int64_t)w * stride];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// One workgroup of 1024 threads per component j. Thread (band t = tid % 256,
+// slice sl = tid / 256) reduces its slice of the chunk sums and of V^T vbar;
+// the slices are added in slice order through LDS; w_j = V u is formed one
+// row per wave step with a wave-wide sum. Every reduction has a fixed order.
+__global__ __launch_bounds__(kWThreads) void bwd_w_kernel(int m, int k, int nchunks, int kg,
+                                                          const double *__restrict__ part,
+                                                          const float *__restrict__ lam,
+                                                          const float *__restrict__ V,
+                                                          const float *__restrict__ dVk,
+                                                          double *__restrict__ wbuf, double *__restrict__ sums)
+{
+    __shared__ double red[kWSlices][256];
     __shared__ double vb[256];
     __shared__ double u[256];
-    const int t = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int t = tid & 255, sl = tid >> 8;
     const int j = blockIdx.x;
     const int g = j / kCompGroup, jj = j % kCompGroup;
     const int64_t ps = part_stride(m);
-    if (t < m) {
-        double a = 0.0;
-        for (int w = 0; w < nchunks; ++w) a += part[((int64_t)w * kg + g) * ps + t * kCompGroup + jj];
-        if (dVk) a += (double)dVk[(int64_t)t * k + j];
-        vb[t] = a;
+    const int64_t cstride = (int64_t)kg * ps;
+    // vbar_j = sum over chunks of X^T Qbar[:, j], plus Vbar_k[:, j].
+    if (t < m) red[sl][t] = slice_sum(part + (int64_t)g * ps + t * kCompGroup + jj, cstride, nchunks, sl);
+    __syncthreads();
+    if (tid < m) {
+        double a = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+        if (dVk) a += (double)dVk[(int64_t)tid * k + j];
+        vb[tid] = a;
     }
     __syncthreads();
+    // (V^T vbar)_t over rows b = sl, sl + 4, ...
     if (t < m) {
-        double T = 0.0;
-        for (int b = 0; b < m; ++b) T += (double)V[(int64_t)b * m + t] * vb[b];
-        const double li = (double)lam[t], lj = (double)lam[j];
-        u[t] = (t == j || li == lj) ? 0.0 : T / (lj - li);
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        int b = sl, q = 0;
+        for (; b < m; b += kWSlices, q = (q + 1) & 3) a[q] += (double)V[(int64_t)b * m + t] * vb[b];
+        red[sl][t] = (a[0] + a[1]) + (a[2] + a[3]);
     }
     __syncthreads();
-    if (t < m) {
-        double a = 0.0;
-        for (int i = 0; i < m; ++i) a += (double)V[(int64_t)t * m + i] * u[i];
-        wbuf[(int64_t)t * k + j] = a;
+    if (tid < m) {
+        const double T = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+        const double li = (double)lam[tid], lj = (double)lam[j];
+        u[tid] = (tid == j || li == lj) ? 0.0 : T / (lj - li);
+    }
+    __syncthreads();
+    // w_j[a] = sum_i V[a][i] u[i]: wave `wave` takes rows wave, wave + 16, ...
+    for (int a = wave; a < m; a += kWThreads / 64) {
+        double x = 0.0;
+        for (int i = lane; i < m; i += 64) x += (double)V[(int64_t)a * m + i] * u[i];
+        x = wave_sum(x);
+        if (lane == 0) wbuf[(int64_t)a * k + j] = x;
     }
     if (j == 0) {
-        // sums[0 .. m) = 1^T X, sums[m .. m+k) = 1^T Qbar, in chunk order.
-        for (int b = t; b < m; b += kThreads) {
-            double a = 0.0;
-            for (int w = 0; w < nchunks; ++w) a += part[((int64_t)w * kg) * ps + kCompGroup * m + kCompGroup + b];
-            sums[b] = a;
-        }
-        for (int c = t; c < k; c += kThreads) {
-            double a = 0.0;
-            for (int w = 0; w < nchunks; ++w)
-                a += part[((int64_t)w * kg + c / kCompGroup) * ps + kCompGroup * m + c % kCompGroup];
-            sums[m + c] = a;
-        }
+        // sums[0 .. m) = 1^T X, sums[m .. m+k) = 1^T Qbar.
+        __syncthreads();
+        if (t < m) red[sl][t] = slice_sum(part + kCompGroup * m + kCompGroup + t, cstride, nchunks, sl);
+        __syncthreads();
+        if (tid < m) sums[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+        __syncthreads();
+        if (t < k) red[sl][t] = slice_sum(part + (int64_t)(t / kCompGroup) * ps + kCompGroup * m + t % kCompGroup,
+                                          cstride, nchunks, sl);
+        __syncthreads();
+        if (tid < k) sums[m + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
     }
 }
 
@@ -188,31 +225,44 @@ __global__ __launch_bounds__(kThreads) void bwd_apply_kernel(const float *__rest
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
 
+    // Slab kc of the augmented operand: thread tid holds column kc + tid % 32
+    // of pixel rows tid / 32 + 8 i (raw values; centred when staged), and
+    // rows kc .. kc+31 of G at column tid.
+    constexpr int kRowsPer = kApplyPix / (kThreads / kApplyK);
+    const int kk0 = tid % kApplyK, pr0 = tid / kApplyK;
+    float va[kRowsPer], vg[kApplyK];
+    auto load = [&](int kc) {
+        const int c = kc + kk0;
+#pragma unroll
+        for (int i = 0; i < kRowsPer; ++i) {
+            const int64_t p = base + pr0 + (kThreads / kApplyK) * i;
+            float v = 0.f;
+            if (p < n) {
+                if (c < m) v = Y[p * ld + c];
+                else if (c < m + k) v = dQ ? dQ[p * k + (c - m)] : 0.f;
+                else if (c == m + k) v = 1.f;
+            }
+            va[i] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < kApplyK; ++r) {
+            const int cr = kc + r;
+            vg[r] = (cr < K && tid < m) ? G[(int64_t)cr * m + tid] : 0.f;
+        }
+    };
+    load(0);
     for (int kc = 0; kc < K; kc += kApplyK) {
         __syncthreads();
-        // A stage: pixel rows of the augmented operand [X | Qbar | 1].
         {
-            const int kk = tid % kApplyK;
-            const int c = kc + kk;
+            const int c = kc + kk0;
             const float mu = c < m ? mean[c] : 0.f;
-            for (int pr = tid / kApplyK; pr < kApplyPix; pr += kThreads / kApplyK) {
-                const int64_t p = base + pr;
-                float v = 0.f;
-                if (p < n) {
-                    if (c < m) v = Y[p * ld + c] - mu;
-                    else if (c < m + k) v = dQ ? dQ[p * k + (c - m)] : 0.f;
-                    else if (c == m + k) v = 1.f;
-                }
-                At[pr * kApplyPitch + kk] = v;
-            }
-        }
-        // B stage: rows kc .. kc+31 of G.
-        for (int e = tid; e < kApplyK * 256; e += kThreads) {
-            const int r = e / 256, col = e % 256;
-            const int c = kc + r;
-            Bt[e] = (c < K && col < m) ? G[(int64_t)c * m + col] : 0.f;
+#pragma unroll
+            for (int i = 0; i < kRowsPer; ++i) At[(pr0 + (kThreads / kApplyK) * i) * kApplyPitch + kk0] = va[i] - mu;
+#pragma unroll
+            for (int r = 0; r < kApplyK; ++r) Bt[r * 256 + tid] = vg[r];
         }
         __syncthreads();
+        if (kc + kApplyK < K) load(kc + kApplyK);
 #pragma unroll 4
         for (int s = 0; s < kApplyK / 2; ++s) {
             const int kk = 2 * s + (lane >> 5);
@@ -248,8 +298,8 @@ BwdPlan bwd_plan(int64_t n, int m, int k)
 {
     BwdPlan p;
     p.kg = (k + kCompGroup - 1) / kCompGroup;
-    int64_t nch = (n + 255) / 256;
-    if (nch > 256) nch = 256;
+    int64_t nch = (n + 63) / 64;
+    if (nch > 1024) nch = 1024;
     const int64_t per = (int64_t)p.kg * part_stride(m) * (int64_t)sizeof(double);
     const int64_t cap = ((int64_t)32 << 20) / (per > 0 ? per : 1);
     if (nch > cap) nch = cap;
@@ -270,7 +320,7 @@ hipError_t launch_backward(const float *Y, int64_t n, int m, int64_t ld, const f
 {
     hipLaunchKernelGGL(bwd_reduce_kernel, dim3((unsigned)p.nchunks, (unsigned)p.kg), dim3(kThreads), 0, st, Y, n, m,
                        ld, mean, dQ, k, p.chunk, p.kg, part);
-    hipLaunchKernelGGL(bwd_w_kernel, dim3((unsigned)k), dim3(kThreads), 0, st, m, k, p.nchunks, p.kg,
+    hipLaunchKernelGGL(bwd_w_kernel, dim3((unsigned)k), dim3(kWThreads), 0, st, m, k, p.nchunks, p.kg,
                        (const double *)part, lam, V, dVk, wbuf, sums);
     const unsigned tb = (unsigned)((m + 15) / 16);
     hipLaunchKernelGGL(bwd_g_kernel, dim3(tb, tb), dim3(kThreads), 0, st, n, m, k, V, dEig, (const double *)wbuf, G);
