@@ -202,7 +202,16 @@ __global__ __launch_bounds__(kThreads) void bwd_r_kernel(int64_t n, int m, int k
             G[(int64_t)(m + j) * m + c] = v;
             r += sums[m + j] * (double)v;
         }
-        for (int b = 0; b < m; ++b) r += sums[b] * (double)G[(int64_t)b * m + c];
+        // Eight interleaved partial sums (eight loads in flight), added in a
+        // fixed order.
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = 0;
+        for (; b + 8 <= m; b += 8) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] += sums[b + i] * (double)G[(int64_t)(b + i) * m + c];
+        }
+        for (int i = 0; b < m; ++b, ++i) a[i] += sums[b] * (double)G[(int64_t)b * m + c];
+        r += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         G[(int64_t)(m + k) * m + c] = (float)(-r / (double)n);
     }
 }
