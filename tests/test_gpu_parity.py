@@ -234,6 +234,30 @@ def test_projection_direct(pca):
     assert np.abs(host(Q) - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n,m,k,u16", [(1000, 224, 10, False), (33, 64, 17, False), (70001, 256, 16, False),
+                                       (5003, 224, 10, True), (777, 4, 3, False), (500, 2, 2, False),
+                                       (4096, 128, 32, False)])
+def test_projection_shapes(pca, n, m, k, u16):
+    """pca_project on aligned (4 bands a load) and unaligned rows, float32 and
+    uint16, pixel counts that are not a multiple of the 32-pixel tile or that
+    leave most workgroups without a tile, 1 to 64 K steps (the second band
+    half empty for 2 and 4 bands), and k up to two 16-column groups."""
+    say(f"pca_project n={n} m={m} k={k} u16={u16}")
+    rng = np.random.default_rng(n + m + k)
+    if u16:
+        Yh = synth.radiance_cube_u16(rng, n, m, 6, 1.0)
+    else:
+        Yh = synth.mixture_cube(rng, n, m, min(6, m), 1.0, 0.01)
+    mu = oracle.band_mean(Yh).astype(np.float32)
+    Vh = synth.haar_orthogonal(rng, m).astype(np.float32)
+    Q = torch.empty(n, k, dtype=torch.float32, device="cuda")
+    pca.pca_project(dev(Yh), dev(mu), dev(Vh), k, Q)
+    ref = oracle.project(oracle.center(Yh, mu.astype(np.float64)), Vh, k)
+    err = np.abs(host(Q) - ref).max() / np.abs(ref).max()
+    say(f"  max rel err {err:.2e}")
+    assert err <= 1e-5
+
+
 def test_deterministic(pca):
     say("determinism")
     d = synth.make_config("c2")
