@@ -282,6 +282,45 @@ def bench_grad(P, synth, torch, args):
     return 0
 
 
+def bench_sweep(P, synth, torch, args):
+    """The paper's synthetic sweep shapes (Section 6): 100^2 .. 500^2 pixels x
+    50 bands and 300^2 pixels x 20 .. 200 bands, 10-endmember mixtures at 70 dB
+    SNR, projection onto the first eigenvector as in the paper's designs; the
+    FP32 and split-bfloat16 pipelines, each cube resident in HBM."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity_utils import report
+    oracle = None
+    if not args.no_accuracy:
+        import oracle as _oracle
+        oracle = _oracle
+    k = 1
+    rows = []
+    for i, (n, m) in enumerate(synth.SWEEP_SHAPES):
+        Yh = synth.snr_mixture_cube(np.random.default_rng(5000 + i), n, m)
+        Yd = torch.from_numpy(Yh).cuda()
+        ref = oracle.pca(Yh, k) if oracle is not None else None
+        rec = dict(pixels=n, bands=m)
+        for mode in ("f32", "bf16x3"):
+            pipe = P.PCAPipeline(n, m, k, mode)
+            ms, _ = time_pipeline(P, torch, pipe, Yd, args.steps, args.warmup)
+            info = P.read_info(pipe.info)
+            rec[mode] = dict(ms=round(ms, 4), value=round(n * m / (ms * 1e-3) / 1e6, 1), sweeps=info["sweeps"])
+            if ref is not None:
+                r = report(pipe.eigvals.cpu().numpy(), pipe.V.cpu().numpy(), pipe.Q.cpu().numpy(), ref, k)
+                rec[mode].update(eig_err=r["eig"], angle_err=r["angle"], proj_err=r["proj"])
+        rows.append(rec)
+        log("sweep", json.dumps(rec))
+        del Yd, pipe
+    out = dict(metric=METRIC, value=None, unit="Mpixel·band/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload="the paper's sweep shapes: 100^2..500^2 px x 50 bands, 300^2 px x 20..200 bands, "
+                                    "70 dB SNR mixtures, k=1"),
+               shapes=rows)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,9 +329,9 @@ def main(argv=None):
     ap.add_argument("--modes", default="f32,bf16x3,bf16x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--workload", choices=("cube224", "batch64", "grad"), default="cube224",
+    ap.add_argument("--workload", choices=("cube224", "batch64", "grad", "sweep"), default="cube224",
                     help="cube224: the 224-band 1024x1024 cube (the reported line); batch64: the 64-cube batch; "
-                         "grad: the differentiation form (forward + adjoint)")
+                         "grad: the differentiation form (forward + adjoint); sweep: the paper's sweep shapes")
     ap.add_argument("--autotune", action="store_true", help="batch64: tune the tile shapes first")
     ap.add_argument("--lanes", type=int, default=1,
                     help="batch64: sub-batches by band count, one pca_batched call and HIP stream each")
@@ -321,6 +360,8 @@ def main(argv=None):
         return bench_batch(P, synth, torch, args)
     if args.workload == "grad":
         return bench_grad(P, synth, torch, args)
+    if args.workload == "sweep":
+        return bench_sweep(P, synth, torch, args)
     log("generating the 224-band cube ...")
     d = synth.make_config("c3")
     k = d["k"]

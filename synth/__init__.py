@@ -17,5 +17,7 @@ from .cubes import (  # noqa: F401
     planted_cube,
     planted_spectrum,
     radiance_cube_u16,
+    SWEEP_SHAPES,
+    snr_mixture_cube,
     random_symmetric,
 )

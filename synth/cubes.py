@@ -78,6 +78,26 @@ def mixture_cube(rng, n_pixels: int, bands: int, r: int, alpha: float,
     return Y
 
 
+def snr_mixture_cube(rng, n_pixels: int, bands: int, r: int = 10, snr_db: float = 70.0,
+                     dtype=np.float32) -> np.ndarray:
+    """Linear-mixing cube (Dirichlet(1) abundances of r endmember spectra)
+    with white Gaussian noise at a given signal-to-noise ratio: the noise
+    standard deviation is the root-mean-square of the noise-free cube times
+    10^(-snr_db / 20) (the shape of the paper's synthetic sweeps, Section 6,
+    on this module's own spectra)."""
+    Y = mixture_cube(rng, n_pixels, bands, r, 1.0, 0.0, dtype=np.float64)
+    sigma = float(np.sqrt(np.mean(Y * Y))) * 10.0 ** (-snr_db / 20.0)
+    for p0 in range(0, n_pixels, _CHUNK):
+        n = min(_CHUNK, n_pixels - p0)
+        Y[p0:p0 + n] += sigma * rng.standard_normal((n, bands))
+    return Y.astype(dtype)
+
+
+# The paper's synthetic sweeps (Section 6): square scenes of 100^2 .. 500^2
+# pixels with 50 bands, and 300^2 pixels with 20, 30, 100 and 200 bands.
+SWEEP_SHAPES = [(s * s, 50) for s in (100, 200, 300, 400, 500)] + [(300 * 300, b) for b in (20, 30, 100, 200)]
+
+
 def radiance_cube_u16(rng, n_pixels: int, bands: int, r: int, alpha: float,
                       offset: float = 500.0, scale: float = 64000.0) -> np.ndarray:
     """uint16 radiance cube: offset + scale * (A E), with Poisson-like noise.
