@@ -742,6 +742,171 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
     }
 }
 
+// Band-sequential float32 cubes with 16-byte aligned band rows (ld and the
+// pixel count multiples of 4), split-bfloat16 forms: the stages are copied
+// straight into LDS, as in cov_partial_dma_kernel. A copy moves 8 band rows
+// x 32 pixels (lane l: band 8 q + l / 8, pixels 4 (l mod 8) .. +3, landing at
+// slot + 16 l bytes), 4 copies a wave and 32 a stage, so a ring slot holds 256
+// band rows of the stage's 32 pixels, band-major like the tiles; centring
+// and the split then read LDS. Bands past the last one and pixels past the
+// chunk (or copied from its start in their place) are masked to zero.
+constexpr int kBsqCopies = 4;   // copies per wave per stage
+
+template <int MODE, int S>
+__global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
+    const float *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+{
+    static_assert(MODE != MODE_F32, "split forms only");
+    constexpr int kHalf = 256 * kBfPitch;
+    constexpr int kSlot = 256 * KT;
+    __shared__ __attribute__((aligned(16))) float raw0[kSlot];
+    __shared__ __attribute__((aligned(16))) float raw1[kSlot];
+    __shared__ __attribute__((aligned(16))) float raw2[kSlot];
+    __shared__ __attribute__((aligned(16))) __bf16 hl[2 * kHalf];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int pp = tid & 15;      // pixel pair within a stage
+    const int bg = tid >> 4;      // band group: bands bg + 32 j
+    const int64_t c = blockIdx.x;
+    const int64_t pbeg = c * chunk;
+    const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
+    const int64_t nst = (pend - pbeg + KT - 1) / KT;
+    // Staggered walk over the chunk's stages (see cov_partial_dma_kernel).
+    const int64_t rot = (c * nst) / gridDim.x;
+    auto first_pixel = [&](int64_t t) -> int64_t {
+        const int64_t tt = t < nst ? (t + rot < nst ? t + rot : t + rot - nst) : 0;
+        return pbeg + tt * KT;
+    };
+
+    float sh[8];
+    double sums[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int b = bg + 32 * j;
+        sh[j] = b < m ? Y[(int64_t)b * ld + pbeg] : 0.f;
+        sums[j] = 0.0;
+    }
+    asm volatile("" ::: "memory");   // the shift loads stay ahead of the copies
+
+    auto issue = [&](float *R, int64_t t) {
+        const int64_t p = first_pixel(t) + 4 * (lane & 7);
+#pragma unroll
+        for (int i = 0; i < kBsqCopies; ++i) {
+            const int q = wave + kDmaWaves * i;                 // copy index: band rows 8 q .. 8 q + 7
+            const int b = 8 * q + (lane >> 3);
+            const bool ok = t < nst && b < m && p < pend;      // p < pend <= n, p and n multiples of 4
+            const float *src = ok ? Y + (int64_t)b * ld + p : Y;
+            __builtin_amdgcn_global_load_lds(static_cast<const void *>(src), static_cast<void *>(R + 8 * q * KT), 16,
+                                             0, 0);
+        }
+    };
+
+    f32x16 acc[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[e][r] = 0.f;
+    }
+    const int nbl = nb * (nb + 1) / 2;
+    int offI[S], offJ[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        int bi = 0, bj = 0;
+        if (kDmaWaves * e + wave < nbl) block_of_id(kDmaWaves * e + wave, bi, bj);
+        offI[e] = (32 * bi + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
+        offJ[e] = (32 * bj + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
+    }
+
+    auto centre = [&](const float *R, int64_t t) {
+        const int64_t p0 = first_pixel(t) + 2 * pp;
+        const bool v0 = t < nst && p0 < pend, v1 = t < nst && p0 + 1 < pend;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int b = bg + 32 * j;
+            if (b >= mpad) continue;
+            const f32x2 raw = *reinterpret_cast<const f32x2 *>(&R[b * KT + 2 * pp]);
+            const float x0 = (b < m && v0) ? raw[0] - sh[j] : 0.f;
+            const float x1 = (b < m && v1) ? raw[1] - sh[j] : 0.f;
+            sums[j] += (double)(x0 + x1);
+            const f32x2 xv = {x0, x1};
+            const bf16x2 hh = __builtin_convertvector(xv, bf16x2);
+            const f32x2 r = xv - __builtin_convertvector(hh, f32x2);
+            const bf16x2 ll = __builtin_convertvector(r, bf16x2);
+            *reinterpret_cast<bf16x2 *>(&hl[b * kBfPitch + 2 * pp]) = hh;
+            *reinterpret_cast<bf16x2 *>(&hl[kHalf + b * kBfPitch + 2 * pp]) = ll;
+        }
+    };
+
+    auto products = [&]() {
+#pragma unroll
+        for (int kk = 0; kk < KT / 16; ++kk) {
+#pragma unroll
+            for (int e = 0; e < S; ++e) {
+                const bf16x8 hi_i = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
+                const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
+                const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
+                const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
+                f32x16 a = acc[e];
+                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
+                if constexpr (MODE == MODE_BF16X4)
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
+                acc[e] = a;
+            }
+        }
+    };
+
+    // As in cov_partial_dma_kernel: wait for this stage's copies, barrier,
+    // start the copies two stages ahead into the slot read last step,
+    // centre and split, barrier, multiply.
+    auto step = [&](float *cur, float *nxt, int64_t st) {
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(kBsqCopies));
+        lds_barrier();
+        issue(nxt, st + 2);
+        centre(cur, st);
+        lds_barrier();
+        products();
+    };
+
+    issue(raw0, 0);
+    issue(raw1, 1);
+    for (int64_t st = 0; st < nst; st += kRing) {
+        step(raw0, raw2, st);
+        step(raw1, raw0, st + 1);
+        step(raw2, raw1, st + 2);
+    }
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    __syncthreads();
+
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        if (kDmaWaves * e + wave < nbl) {
+            int bi, bj;
+            block_of_id(kDmaWaves * e + wave, bi, bj);
+            float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) dst[r * 64] = acc[e][r];
+        }
+    }
+    // Band sums: the 16 threads of a band group (consecutive lanes) hold
+    // different pixels of the same bands.
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        double t = sums[j];
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) t += __shfl_xor(t, o, 16);
+        const int b = bg + 32 * j;
+        if (pp == 0 && b < mpad) {
+            partSum[c * mpad + b] = t;
+            partShift[c * mpad + b] = sh[j];
+        }
+    }
+}
+
 // Pass 2a: grid (block, chunk group). Every workgroup forms the band means of
 // its block's 64 bands (all chunks, float64, fixed order: identical in every
 // workgroup), then the centred second moment of its range of chunks.
@@ -1007,10 +1172,41 @@ hipError_t launch_bsq_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan 
     return hipGetLastError();
 }
 
+template <int MODE>
+hipError_t launch_bsq_dma_m(const float *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
+                            double *partSum, float *partShift, hipStream_t st)
+{
+    const dim3 grid((unsigned)p.nchunks), block(kDmaThreads);
+#define PCA_BSQ_DMA(S)                                                                                             \
+    hipLaunchKernelGGL((cov_partial_bsq_dma_kernel<MODE, S>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb,      \
+                       p.nblk, p.mpad, partS, partSum, partShift)
+    switch (dma_slots(p.nb)) {
+    case 2: PCA_BSQ_DMA(2); break;
+    case 3: PCA_BSQ_DMA(3); break;
+    case 4: PCA_BSQ_DMA(4); break;
+    default: PCA_BSQ_DMA(5); break;
+    }
+#undef PCA_BSQ_DMA
+    return hipGetLastError();
+}
+
+// Band-sequential float32 cubes whose band rows can be copied 16 bytes a
+// lane.
+inline bool bsq_dma_ok(const void *Y, int mode, int64_t n, int64_t ld)
+{
+    return mode != MODE_F32 && (reinterpret_cast<uintptr_t>(Y) % 16 == 0) && (ld % 4 == 0) && (n % 4 == 0);
+}
+
 template <typename T>
 hipError_t launch_partial_bsq(const T *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p, float *partS,
                               double *partSum, float *partShift, hipStream_t st)
 {
+    if constexpr (sizeof(T) == 4) {
+        if (bsq_dma_ok(Y, mode, n, ld)) {
+            if (mode == MODE_BF16X3) return launch_bsq_dma_m<MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
+            return launch_bsq_dma_m<MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
+        }
+    }
     switch (mode) {
     case MODE_F32: return launch_bsq_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, st);
     case MODE_BF16X3: return launch_bsq_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);

@@ -61,8 +61,11 @@ def cov(P, Y, mode, layout, centered=False):
 # (pixels, bands, band-stride padding): ragged pixel counts (not a multiple of
 # the 32-pixel stage), band counts on both sides of the 32-band blocks, the
 # band limit (256, where the float32 products take several passes), padding.
+# Pixel counts and band strides that are multiples of 4 take the LDS-copy
+# kernel in the split forms (one stage, ragged chunks, every
+# band count class), the others the register-staged one.
 SHAPES = [(1000, 2, 0), (3001, 37, 5), (4096, 64, 0), (2500, 129, 3), (20001, 224, 0), (5000, 255, 1),
-          (3333, 256, 0)]
+          (3333, 256, 0), (4, 8, 0), (2016, 64, 0), (20000, 224, 0), (5000, 255, 4), (2048, 256, 0), (9996, 33, 8)]
 
 
 @pytest.mark.parametrize("n,m,pad", SHAPES)
