@@ -16,6 +16,13 @@
 //   N_2 = sum_w [S_w + t_w e_w^T + e_w t_w^T + n_w e_w e_w^T]
 //       = sum_p (y_p - mu)(y_p - mu)^T          (exact algebra),
 //   C = N_2 / (N - 1), mirrored to a full symmetric matrix.
+//
+// Pass-1 kernels by layout: cov_partial_dma_kernel (band-interleaved float32
+// or uint16 rows of whole 16-byte pieces, copied straight into LDS),
+// cov_partial_bsq_dma_kernel (band-sequential float32, split forms, likewise),
+// cov_partial_bsq_kernel (other band-sequential cubes, register-staged),
+// cov_partial_kernel (any other band-interleaved layout, register-staged) and
+// cov_partial_batched_kernel (the batched form's persistent launch).
 #include "common.hpp"
 #include "kernels.hpp"
 #include "loader.hpp"
