@@ -19,7 +19,8 @@
 //
 // Pass-1 kernels by layout: cov_partial_dma_kernel (band-interleaved float32
 // or uint16 rows of whole 16-byte pieces, copied straight into LDS),
-// cov_partial_bsq_dma_kernel (band-sequential float32, split forms, likewise),
+// cov_partial_bsq_dma_kernel (band-sequential rows of whole 16-byte pieces,
+// split forms, likewise),
 // cov_partial_bsq_kernel (other band-sequential cubes, register-staged),
 // cov_partial_kernel (any other band-interleaved layout, register-staged) and
 // cov_partial_batched_kernel (the batched form's persistent launch).
@@ -749,27 +750,32 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
     }
 }
 
-// Band-sequential float32 cubes with 16-byte aligned band rows (ld and the
-// pixel count multiples of 4), split-bfloat16 forms: the stages are copied
-// straight into LDS, as in cov_partial_dma_kernel. A copy moves 8 band rows
-// x 32 pixels (lane l: band 8 q + l / 8, pixels 4 (l mod 8) .. +3, landing at
-// slot + 16 l bytes), 4 copies a wave and 32 a stage, so a ring slot holds 256
-// band rows of the stage's 32 pixels, band-major like the tiles; centring
-// and the split then read LDS. Bands past the last one and pixels past the
-// chunk (or copied from its start in their place) are masked to zero.
-constexpr int kBsqCopies = 4;   // copies per wave per stage
-
-template <int MODE, int S>
+// Band-sequential cubes with 16-byte aligned band rows (ld and the pixel
+// count multiples of 16 bytes' worth of pixels), split-bfloat16 forms: the
+// stages are copied straight into LDS, as in cov_partial_dma_kernel. A copy
+// moves 16 bytes a lane, kPix pixels (4 float32 or 8 uint16): lane l takes
+// band kRows q + l / (32 / kPix), pixels kPix (l mod (32 / kPix)) onwards,
+// landing at slot + 16 l bytes, so one copy is kRows = 2 kPix band rows of
+// the stage's 32 pixels; 256 / kRows copies a stage, shared by the 8 waves.
+// A ring slot holds 256 band rows x 32 pixels, band-major like the tiles;
+// centring and the split then read LDS. Bands past the last one and pixels
+// past the chunk (or copied from its start in their place) are masked to
+// zero.
+template <typename T, int MODE, int S>
 __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
-    const float *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
+    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
     float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
 {
     static_assert(MODE != MODE_F32, "split forms only");
+    constexpr int kPix = 16 / (int)sizeof(T);        // pixels per lane and copy
+    constexpr int kLanesPerRow = KT / kPix;          // 8 (float32) or 4 (uint16)
+    constexpr int kRows = 64 / kLanesPerRow;         // band rows per copy
+    constexpr int kBsqCopies = 256 / kRows / kDmaWaves;   // copies per wave per stage: 4 or 2
     constexpr int kHalf = 256 * kBfPitch;
     constexpr int kSlot = 256 * KT;
-    __shared__ __attribute__((aligned(16))) float raw0[kSlot];
-    __shared__ __attribute__((aligned(16))) float raw1[kSlot];
-    __shared__ __attribute__((aligned(16))) float raw2[kSlot];
+    __shared__ __attribute__((aligned(16))) T raw0[kSlot];
+    __shared__ __attribute__((aligned(16))) T raw1[kSlot];
+    __shared__ __attribute__((aligned(16))) T raw2[kSlot];
     __shared__ __attribute__((aligned(16))) __bf16 hl[2 * kHalf];
 
     const int tid = threadIdx.x;
@@ -793,21 +799,23 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int b = bg + 32 * j;
-        sh[j] = b < m ? Y[(int64_t)b * ld + pbeg] : 0.f;
+        sh[j] = b < m ? load_elem(Y + (int64_t)b * ld + pbeg) : 0.f;
         sums[j] = 0.0;
     }
     asm volatile("" ::: "memory");   // the shift loads stay ahead of the copies
 
-    auto issue = [&](float *R, int64_t t) {
-        const int64_t p = first_pixel(t) + 4 * (lane & 7);
+    auto issue = [&](T *R, int64_t t) {
+        const int64_t p = first_pixel(t) + kPix * (lane % kLanesPerRow);
 #pragma unroll
         for (int i = 0; i < kBsqCopies; ++i) {
-            const int q = wave + kDmaWaves * i;                 // copy index: band rows 8 q .. 8 q + 7
-            const int b = 8 * q + (lane >> 3);
-            const bool ok = t < nst && b < m && p < pend;      // p < pend <= n, p and n multiples of 4
-            const float *src = ok ? Y + (int64_t)b * ld + p : Y;
-            __builtin_amdgcn_global_load_lds(static_cast<const void *>(src), static_cast<void *>(R + 8 * q * KT), 16,
-                                             0, 0);
+            const int q = wave + kDmaWaves * i;                 // copy index: band rows kRows q onwards
+            const int b = kRows * q + lane / kLanesPerRow;
+            const bool ok = t < nst && b < m && p < pend;      // p < pend <= n, p and n multiples of kPix
+            const T *src = ok ? Y + (int64_t)b * ld + p : Y;
+            // (void pointers: the host pass drops kernels whose target
+            // builtins take arguments of template-dependent type)
+            __builtin_amdgcn_global_load_lds(static_cast<const void *>(src),
+                                             static_cast<void *>(R + kRows * q * KT), 16, 0, 0);
         }
     };
 
@@ -827,16 +835,25 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
         offJ[e] = (32 * bj + (lane & 31)) * kBfPitch + 8 * (lane >> 5);
     }
 
-    auto centre = [&](const float *R, int64_t t) {
+    auto centre = [&](const T *R, int64_t t) {
         const int64_t p0 = first_pixel(t) + 2 * pp;
         const bool v0 = t < nst && p0 < pend, v1 = t < nst && p0 + 1 < pend;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int b = bg + 32 * j;
             if (b >= mpad) continue;
-            const f32x2 raw = *reinterpret_cast<const f32x2 *>(&R[b * KT + 2 * pp]);
-            const float x0 = (b < m && v0) ? raw[0] - sh[j] : 0.f;
-            const float x1 = (b < m && v1) ? raw[1] - sh[j] : 0.f;
+            float r0, r1;
+            if constexpr (sizeof(T) == 4) {
+                const f32x2 raw = *reinterpret_cast<const f32x2 *>(&R[b * KT + 2 * pp]);
+                r0 = raw[0];
+                r1 = raw[1];
+            } else {
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(&R[b * KT + 2 * pp]);
+                r0 = (float)(w & 0xffffu);
+                r1 = (float)(w >> 16);
+            }
+            const float x0 = (b < m && v0) ? r0 - sh[j] : 0.f;
+            const float x1 = (b < m && v1) ? r1 - sh[j] : 0.f;
             sums[j] += (double)(x0 + x1);
             const f32x2 xv = {x0, x1};
             const bf16x2 hh = __builtin_convertvector(xv, bf16x2);
@@ -870,7 +887,7 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
     // As in cov_partial_dma_kernel: wait for this stage's copies, barrier,
     // start the copies two stages ahead into the slot read last step,
     // centre and split, barrier, multiply.
-    auto step = [&](float *cur, float *nxt, int64_t st) {
+    auto step = [&](T *cur, T *nxt, int64_t st) {
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(kBsqCopies));
         lds_barrier();
         issue(nxt, st + 2);
@@ -1179,13 +1196,13 @@ hipError_t launch_bsq_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan 
     return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t launch_bsq_dma_m(const float *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
+template <typename T, int MODE>
+hipError_t launch_bsq_dma_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
                             double *partSum, float *partShift, hipStream_t st)
 {
     const dim3 grid((unsigned)p.nchunks), block(kDmaThreads);
 #define PCA_BSQ_DMA(S)                                                                                             \
-    hipLaunchKernelGGL((cov_partial_bsq_dma_kernel<MODE, S>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb,      \
+    hipLaunchKernelGGL((cov_partial_bsq_dma_kernel<T, MODE, S>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb,   \
                        p.nblk, p.mpad, partS, partSum, partShift)
     switch (dma_slots(p.nb)) {
     case 2: PCA_BSQ_DMA(2); break;
@@ -1197,22 +1214,21 @@ hipError_t launch_bsq_dma_m(const float *Y, int64_t n, int m, int64_t ld, const 
     return hipGetLastError();
 }
 
-// Band-sequential float32 cubes whose band rows can be copied 16 bytes a
-// lane.
-inline bool bsq_dma_ok(const void *Y, int mode, int64_t n, int64_t ld)
+// Band-sequential cubes whose band rows can be copied 16 bytes a lane
+// (pixels per 16 bytes: 4 float32, 8 uint16).
+inline bool bsq_dma_ok(const void *Y, int elem_bytes, int mode, int64_t n, int64_t ld)
 {
-    return mode != MODE_F32 && (reinterpret_cast<uintptr_t>(Y) % 16 == 0) && (ld % 4 == 0) && (n % 4 == 0);
+    const int64_t per = 16 / elem_bytes;
+    return mode != MODE_F32 && (reinterpret_cast<uintptr_t>(Y) % 16 == 0) && (ld % per == 0) && (n % per == 0);
 }
 
 template <typename T>
 hipError_t launch_partial_bsq(const T *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p, float *partS,
                               double *partSum, float *partShift, hipStream_t st)
 {
-    if constexpr (sizeof(T) == 4) {
-        if (bsq_dma_ok(Y, mode, n, ld)) {
-            if (mode == MODE_BF16X3) return launch_bsq_dma_m<MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
-            return launch_bsq_dma_m<MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
-        }
+    if (bsq_dma_ok(Y, (int)sizeof(T), mode, n, ld)) {
+        if (mode == MODE_BF16X3) return launch_bsq_dma_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
+        return launch_bsq_dma_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
     }
     switch (mode) {
     case MODE_F32: return launch_bsq_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, st);

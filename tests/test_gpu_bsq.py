@@ -91,11 +91,16 @@ def test_bsq_uint16_and_centered(pca):
     n, m = 7000, 96
     u = synth.radiance_cube_u16(np.random.default_rng(31), n, m, 6, 1.0)
     ref = oracle.pca(u, 1)
-    Yb = bsq(u, 2)
-    for mode in ("f32", "bf16x4"):
-        C, mean = cov(pca, Yb, mode, "bsq")
-        assert np.abs(C - ref["C"]).max() / np.abs(ref["C"]).max() <= COV_TOL[mode], mode
-        assert np.abs(mean - ref["mean"]).max() <= 1e-6 * np.abs(ref["mean"]).max()
+    # band stride 7002: register-staged; 7008 (a multiple of 8 uint16): LDS
+    # copies in the split forms
+    for pad in (2, 8):
+        Yb = bsq(u, pad)
+        for mode in ("f32", "bf16x3", "bf16x4"):
+            C, mean = cov(pca, Yb, mode, "bsq")
+            err = np.abs(C - ref["C"]).max() / np.abs(ref["C"]).max()
+            say(f"  pad {pad} {mode}: {err:.2e}")
+            assert err <= COV_TOL[mode], (pad, mode, err)
+            assert np.abs(mean - ref["mean"]).max() <= 1e-6 * np.abs(ref["mean"]).max()
     # centred input: C = Y^T Y / (N - 1)
     X = (u.astype(np.float64) - u.astype(np.float64).mean(0)).astype(np.float32)
     Cc, _ = cov(pca, bsq(X), "f32", "bsq", centered=True)
