@@ -21,8 +21,7 @@
 //               X^T Qbar, 1^T Qbar and 1^T X (X formed on the fly from Y, mu);
 //   bwd_w:      one 1024-thread workgroup per component j: vbar_j (chunk
 //               sums in a fixed order plus Vbar_k), u = F[:, j] o (V^T vbar_j),
-//               w_j = V u;
-//               workgroup 0 also finishes 1^T Qbar and 1^T X;
+//               w_j = V u; one more workgroup finishes 1^T Qbar and 1^T X;
 //   bwd_g:      G[a][b] = 2/(N-1) sym(Cbar)[a][b] in 16 x 16 tiles;
 //   bwd_r:      rows M .. M+k-1 of G = V_k^T, row M+k = -(1^T Xbar) / N;
 //   bwd_apply:  dY = [X | Qbar | 1] G, one GEMM over all pixels with
@@ -93,28 +92,30 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float *__res
     if (t < kCompGroup) dst[kCompGroup * m + t] = sq;
 }
 
-constexpr int kWThreads = 1024;     // bwd_w: 4 slices x 256 bands
-constexpr int kWSlices = 4;
+constexpr int kWThreads = 1024;     // bwd_w: slices x bands
+constexpr int kWMaxSlices = 8;
 
-// Slice sl of sum_w p[w * stride] over w < count: w = sl, sl + 4, ...,
-// as eight interleaved partial sums added in a fixed order (eight loads in
-// flight).
-__device__ inline double slice_sum(const double *__restrict__ p, int64_t stride, int count, int sl)
+// Slice sl (of ns) of sum_w p[w * stride] over w < count: w = sl, sl + ns,
+// ..., as eight interleaved partial sums added in a fixed order (eight loads
+// in flight).
+__device__ inline double slice_sum(const double *__restrict__ p, int64_t stride, int count, int sl, int ns)
 {
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int w = sl;
-    for (; w + (8 - 1) * kWSlices < count; w += 8 * kWSlices) {
+    for (; w + 7 * ns < count; w += 8 * ns) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] += p[(int64_t)(w + i * kWSlices) * stride];
+        for (int i = 0; i < 8; ++i) a[i] += p[(int64_t)(w + i * ns) * stride];
     }
-    for (int i = 0; w < count; w += kWSlices, ++i) a[i] += p[(int64_t)w * stride];
+    for (int i = 0; w < count; w += ns, ++i) a[i] += p[(int64_t)w * stride];
     return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
-// One workgroup of 1024 threads per component j. Thread (band t = tid % 256,
-// slice sl = tid / 256) reduces its slice of the chunk sums and of V^T vbar;
-// the slices are added in slice order through LDS; w_j = V u is formed one
-// row per wave step with a wave-wide sum. Every reduction has a fixed order.
+// Workgroups 0 .. k-1: one per component j, 1024 threads. Thread (band t,
+// slice sl) reduces its slice of the chunk sums and of V^T vbar (8 slices of
+// 128 bands, or 4 of 256); the slices are added in slice order through LDS;
+// w_j = V u is formed one row per wave step with a wave-wide sum.
+// Workgroup k: the chunk sums 1^T X and 1^T Qbar. Every reduction has a
+// fixed order.
 __global__ __launch_bounds__(kWThreads) void bwd_w_kernel(int m, int k, int nchunks, int kg,
                                                           const double *__restrict__ part,
                                                           const float *__restrict__ lam,
@@ -122,34 +123,53 @@ __global__ __launch_bounds__(kWThreads) void bwd_w_kernel(int m, int k, int nchu
                                                           const float *__restrict__ dVk,
                                                           double *__restrict__ wbuf, double *__restrict__ sums)
 {
-    __shared__ double red[kWSlices][256];
+    __shared__ double red[kWMaxSlices][256];
     __shared__ double vb[256];
     __shared__ double u[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int t = tid & 255, sl = tid >> 8;
+    const int ns = m <= 128 ? 8 : 4;
+    const int bw = kWThreads / ns;               // 128 or 256 bands per slice
+    const int t = tid % bw, sl = tid / bw;
     const int j = blockIdx.x;
-    const int g = j / kCompGroup, jj = j % kCompGroup;
     const int64_t ps = part_stride(m);
     const int64_t cstride = (int64_t)kg * ps;
+    auto combine = [&](int b) {
+        double a = 0.0;
+        for (int q = 0; q < ns; ++q) a += red[q][b];
+        return a;
+    };
+    if (j == k) {
+        // sums[0 .. m) = 1^T X, sums[m .. m+k) = 1^T Qbar.
+        if (t < m) red[sl][t] = slice_sum(part + kCompGroup * m + kCompGroup + t, cstride, nchunks, sl, ns);
+        __syncthreads();
+        if (tid < m) sums[tid] = combine(tid);
+        __syncthreads();
+        if (t < k) red[sl][t] = slice_sum(part + (int64_t)(t / kCompGroup) * ps + kCompGroup * m + t % kCompGroup,
+                                          cstride, nchunks, sl, ns);
+        __syncthreads();
+        if (tid < k) sums[m + tid] = combine(tid);
+        return;
+    }
+    const int g = j / kCompGroup, jj = j % kCompGroup;
     // vbar_j = sum over chunks of X^T Qbar[:, j], plus Vbar_k[:, j].
-    if (t < m) red[sl][t] = slice_sum(part + (int64_t)g * ps + t * kCompGroup + jj, cstride, nchunks, sl);
+    if (t < m) red[sl][t] = slice_sum(part + (int64_t)g * ps + t * kCompGroup + jj, cstride, nchunks, sl, ns);
     __syncthreads();
     if (tid < m) {
-        double a = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+        double a = combine(tid);
         if (dVk) a += (double)dVk[(int64_t)tid * k + j];
         vb[tid] = a;
     }
     __syncthreads();
-    // (V^T vbar)_t over rows b = sl, sl + 4, ...
+    // (V^T vbar)_t over rows b = sl, sl + ns, ...
     if (t < m) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         int b = sl, q = 0;
-        for (; b < m; b += kWSlices, q = (q + 1) & 3) a[q] += (double)V[(int64_t)b * m + t] * vb[b];
+        for (; b < m; b += ns, q = (q + 1) & 3) a[q] += (double)V[(int64_t)b * m + t] * vb[b];
         red[sl][t] = (a[0] + a[1]) + (a[2] + a[3]);
     }
     __syncthreads();
     if (tid < m) {
-        const double T = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+        const double T = combine(tid);
         const double li = (double)lam[tid], lj = (double)lam[j];
         u[tid] = (tid == j || li == lj) ? 0.0 : T / (lj - li);
     }
@@ -160,18 +180,6 @@ __global__ __launch_bounds__(kWThreads) void bwd_w_kernel(int m, int k, int nchu
         for (int i = lane; i < m; i += 64) x += (double)V[(int64_t)a * m + i] * u[i];
         x = wave_sum(x);
         if (lane == 0) wbuf[(int64_t)a * k + j] = x;
-    }
-    if (j == 0) {
-        // sums[0 .. m) = 1^T X, sums[m .. m+k) = 1^T Qbar.
-        __syncthreads();
-        if (t < m) red[sl][t] = slice_sum(part + kCompGroup * m + kCompGroup + t, cstride, nchunks, sl);
-        __syncthreads();
-        if (tid < m) sums[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-        __syncthreads();
-        if (t < k) red[sl][t] = slice_sum(part + (int64_t)(t / kCompGroup) * ps + kCompGroup * m + t % kCompGroup,
-                                          cstride, nchunks, sl);
-        __syncthreads();
-        if (tid < k) sums[m + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
     }
 }
 
@@ -329,7 +337,7 @@ hipError_t launch_backward(const float *Y, int64_t n, int m, int64_t ld, const f
 {
     hipLaunchKernelGGL(bwd_reduce_kernel, dim3((unsigned)p.nchunks, (unsigned)p.kg), dim3(kThreads), 0, st, Y, n, m,
                        ld, mean, dQ, k, p.chunk, p.kg, part);
-    hipLaunchKernelGGL(bwd_w_kernel, dim3((unsigned)k), dim3(kWThreads), 0, st, m, k, p.nchunks, p.kg,
+    hipLaunchKernelGGL(bwd_w_kernel, dim3((unsigned)(k + 1)), dim3(kWThreads), 0, st, m, k, p.nchunks, p.kg,
                        (const double *)part, lam, V, dVk, wbuf, sums);
     const unsigned tb = (unsigned)((m + 15) / 16);
     hipLaunchKernelGGL(bwd_g_kernel, dim3(tb, tb), dim3(kThreads), 0, st, n, m, k, V, dEig, (const double *)wbuf, G);
