@@ -224,7 +224,10 @@ __global__ __launch_bounds__(kThreads) void bwd_r_kernel(int64_t n, int m, int k
     }
 }
 
-__global__ __launch_bounds__(kThreads) void bwd_apply_kernel(const float *__restrict__ Y, int64_t n, int m,
+// NT: 32-column tiles of dY held per wave (4 for up to 128 bands, else 8;
+// fewer accumulators leave room for more waves per SIMD).
+template <int NT>
+__global__ __launch_bounds__(kThreads, NT == 4 ? 2 : 1) void bwd_apply_kernel(const float *__restrict__ Y, int64_t n, int m,
                                                              int64_t ld, const float *__restrict__ mean,
                                                              const float *__restrict__ dQ, int k,
                                                              const float *__restrict__ G, float *__restrict__ dY,
@@ -236,9 +239,9 @@ __global__ __launch_bounds__(kThreads) void bwd_apply_kernel(const float *__rest
     const int64_t base = (int64_t)blockIdx.x * kApplyPix;
     const int K = m + k + 1;
     const int ntiles = (m + 31) / 32;
-    f32x16 acc[8];
+    f32x16 acc[NT];
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
 
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void bwd_apply_kernel(const float *__rest
             const int kk = 2 * s + (lane >> 5);
             const float a = At[(32 * wave + (lane & 31)) * kApplyPitch + kk];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < NT; ++t) {
                 if (t < ntiles) {
                     const float b = Bt[kk * 256 + 32 * t + (lane & 31)];
                     acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
@@ -296,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void bwd_apply_kernel(const float *__rest
     // 32x32 result layout: lane l, register r -> row 8 (r/4) + 4 (l/32) + r%4,
     // column l % 32.
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < NT; ++t) {
         if (t < ntiles) {
             const int col = 32 * t + (lane & 31);
 #pragma unroll
@@ -342,8 +345,13 @@ hipError_t launch_backward(const float *Y, int64_t n, int m, int64_t ld, const f
     const unsigned tb = (unsigned)((m + 15) / 16);
     hipLaunchKernelGGL(bwd_g_kernel, dim3(tb, tb), dim3(kThreads), 0, st, n, m, k, V, dEig, (const double *)wbuf, G);
     hipLaunchKernelGGL(bwd_r_kernel, dim3(1), dim3(kThreads), 0, st, n, m, k, V, (const double *)sums, G);
-    hipLaunchKernelGGL(bwd_apply_kernel, dim3((unsigned)((n + kApplyPix - 1) / kApplyPix)), dim3(kThreads), 0, st, Y,
-                       n, m, ld, mean, dQ, k, (const float *)G, dY, ldd);
+    const dim3 ga((unsigned)((n + kApplyPix - 1) / kApplyPix));
+    if (m <= 128)
+        hipLaunchKernelGGL(bwd_apply_kernel<4>, ga, dim3(kThreads), 0, st, Y, n, m, ld, mean, dQ, k, (const float *)G, dY,
+                           ldd);
+    else
+        hipLaunchKernelGGL(bwd_apply_kernel<8>, ga, dim3(kThreads), 0, st, Y, n, m, ld, mean, dQ, k, (const float *)G, dY,
+                           ldd);
     return hipGetLastError();
 }
 
