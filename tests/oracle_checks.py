@@ -49,6 +49,11 @@ def check_exact_rational(seed=1, lib=None):
     C = oracle.covariance(oracle.center(Y, mu))
     assert max(abs(float(mu_q[b]) - mu[b]) for b in range(m)) <= 1e-14
     assert max(abs(float(C_q[i][j]) - C[i, j]) for i in range(m) for j in range(m)) <= 1e-13
+    # Entry-by-entry form used for sampled checks of full-size results.
+    pairs = [(i, j) for i in range(m) for j in range(m)]
+    ent = oracle.covariance_entries(Y, mu, pairs)
+    assert max(abs(float(C_q[i][j]) - e) for (i, j), e in zip(pairs, ent)) <= 1e-13, \
+        "covariance entries differ from exact rational arithmetic"
 
 
 # --- covariance ------------------------------------------------------------
@@ -188,6 +193,21 @@ def check_sort_and_sign(seed=8, lib=None):
     assert np.all(np.diff(lam) <= 0), "eigenvalues not descending"
     idx = np.argmax(np.abs(V), axis=0)
     assert np.all(V[idx, np.arange(10)] > 0), "sign rule violated"
+    # Exact ties: [[a, b], [b, a]] blocks have eigenvectors (1, -1)/sqrt(2)
+    # (eigenvalue a - b) and (1, 1)/sqrt(2) (a + b), whose two entries have
+    # equal magnitude bit for bit (the rotation of a 45 degree angle has
+    # cos == sin). The sign rule then makes the lower index positive.
+    r = 1.0 / math.sqrt(2.0)
+    lam, V, _ = oracle.jacobi_eigh(np.array([[2.0, -1.0], [-1.0, 2.0]]), lib_path=lib)
+    assert np.array_equal(lam, [3.0, 1.0]) or _rel(lam, [3.0, 1.0], 3.0) <= 1e-15
+    assert _rel(V, [[r, r], [-r, r]], 1.0) <= 1e-15, "tie in the sign rule not resolved to the lowest index"
+    B = np.zeros((4, 4))
+    B[:2, :2] = [[5.0, 2.0], [2.0, 5.0]]      # eigenvalues 7 and 3
+    B[2:, 2:] = [[1.0, -0.5], [-0.5, 1.0]]    # eigenvalues 1.5 and 0.5
+    lam, V, _ = oracle.jacobi_eigh(B, lib_path=lib)
+    ref = np.array([[r, r, 0, 0], [r, -r, 0, 0], [0, 0, r, r], [0, 0, -r, r]])
+    assert _rel(lam, [7.0, 3.0, 1.5, 0.5], 7.0) <= 1e-15
+    assert _rel(V, ref, 1.0) <= 1e-15, "tie in the sign rule not resolved to the lowest index"
 
 
 # --- projection and loss -----------------------------------------------------
@@ -201,6 +221,12 @@ def check_projection_identity(seed=9, lib=None):
     G = Q.T @ Q / (n - 1)
     assert _rel(G, np.diag(r["lam"][:k]), r["lam"][0]) <= 1e-12, "Q^T Q/(N-1) != diag(lam)"
     assert np.max(np.abs(Q.sum(axis=0))) <= 1e-9 * np.abs(Q).max() * n ** 0.5
+    # The row-by-row form used for sampled checks of full-size results: the
+    # same identity over every row.
+    Qr = oracle.project_rows(Y, r["mean"], r["V"], k, np.arange(n))
+    Gr = Qr.T @ Qr / (n - 1)
+    assert _rel(Gr, np.diag(r["lam"][:k]), r["lam"][0]) <= 1e-12, "row-wise Q^T Q/(N-1) != diag(lam)"
+    assert np.max(np.abs(Qr.sum(axis=0))) <= 1e-9 * np.abs(Qr).max() * n ** 0.5
     loss = oracle.reconstruction_loss(Y, k, res=r)
     closed = (n - 1) * (np.trace(r["C"]) - r["lam"][:k].sum())
     assert abs(loss - closed) <= 1e-10 * abs(closed), "reconstruction loss closed form"

@@ -58,6 +58,23 @@ def _sign_negative(V):
     return -po.sign_fix.__wrapped__(V) if hasattr(po.sign_fix, "__wrapped__") else -_ORIG["sign_fix"](V)
 
 
+def _sign_ties_last(V):
+    V = np.array(V, dtype=np.float64, copy=True)
+    a = np.abs(V)[::-1]
+    idx = V.shape[0] - 1 - np.argmax(a, axis=0)      # last index of the maximum
+    sgn = np.where(V[idx, np.arange(V.shape[1])] < 0, -1.0, 1.0)
+    return V * sgn[None, :]
+
+
+def _cov_entries_over_n(Y, mu, pairs):
+    Y = np.asarray(Y, dtype=np.float64)
+    return np.array([np.dot(Y[:, i] - mu[i], Y[:, j] - mu[j]) / Y.shape[0] for i, j in pairs])
+
+
+def _project_rows_uncentred(Y, mu, V, k, rows):
+    return np.asarray(Y, dtype=np.float64)[np.asarray(rows)] @ np.asarray(V, dtype=np.float64)[:, :k]
+
+
 def _project_rows(X, V, k):
     return np.asarray(X, dtype=np.float64) @ np.asarray(V, dtype=np.float64)[:k, :].T
 
@@ -80,7 +97,7 @@ def _centre_adjoint_identity(Xbar):
 
 _ORIG = {name: getattr(po, name) for name in
          ("covariance", "center", "band_mean", "sort_desc", "sign_fix", "project",
-          "_eigh_adjoint", "_centre_adjoint")}
+          "_eigh_adjoint", "_centre_adjoint", "covariance_entries", "project_rows")}
 
 PY_MUTANTS = {
     "covariance divided by N": ("covariance", _cov_over_n),
@@ -88,6 +105,9 @@ PY_MUTANTS = {
     "mean divided by N-1": ("band_mean", _mean_over_n1),
     "eigenvalues sorted ascending": ("sort_desc", _sort_ascending),
     "sign rule inverted": ("sign_fix", _sign_negative),
+    "sign rule ties resolved to the last index": ("sign_fix", _sign_ties_last),
+    "covariance entries divided by N": ("covariance_entries", _cov_entries_over_n),
+    "row-wise projection without centring": ("project_rows", _project_rows_uncentred),
     "projection on rows of V": ("project", _project_rows),
     "eigengap weights with the wrong sign": ("_eigh_adjoint", _eigh_adjoint_flipped),
     "eigh adjoint not symmetrised": ("_eigh_adjoint", _eigh_adjoint_unsym),
