@@ -89,7 +89,12 @@ typedef enum {
      * after the sweeps; it holds one more CU per ~2048/n_bands rows of the
      * eigenvector matrix for the length of the sweeps, so it pays when one
      * cube has the GPU to itself. */
-    PCA_JACOBI_OVERLAP_REPLAY = 2
+    PCA_JACOBI_OVERLAP_REPLAY = 2,
+    /* Run the one-workgroup form (the whole matrix on one CU) whatever the
+     * band count. */
+    PCA_JACOBI_ONE_CU = 4,
+    /* Run the block-cyclic form on many CUs whatever the band count. */
+    PCA_JACOBI_BLOCK = 8
 } pca_jacobi_flag;
 
 /* Written on the device by pca_jacobi_eigh (copy it back to read it). */
@@ -170,13 +175,26 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
 
 /*
  * All eigenpairs of the symmetric C by the cyclic Jacobi method (Section 2,
- * equations (2)-(10)): one workgroup holds the matrix in LDS and applies
- * n_bands/2 disjoint rotations per parallel step in round-robin order (the
- * parallel-rotation property stated at the end of Section 2), n_bands - 1
- * steps per sweep. Rotation angles use equations (2)-(5) with (7) in the
- * cancellation-free form; the flag PCA_JACOBI_FP64_ANGLES evaluates them
- * (and the diagonal) in float64. A rotation is skipped when |a_pq| <= 2^-24 sqrt(|a_pp a_qq|)
- * or |a_pq| <= 2^-24 ||C||_F / n_bands. Stops before a sweep when
+ * equations (2)-(10)), in one of two forms, both applying disjoint rotations
+ * together (the parallel-rotation property stated at the end of Section 2):
+ *   - one workgroup holds the matrix in LDS and applies n_bands/2 rotations
+ *     per parallel step in round-robin order, n_bands - 1 steps per sweep
+ *     (PCA_JACOBI_ONE_CU; the default below 224 bands);
+ *   - block-cyclic: the indices are grouped in blocks of 16, a round-robin
+ *     over the blocks pairs them, and one workgroup per pair of block pairs
+ *     rotates its pair's index pairs and applies the product of those
+ *     rotations to its tiles of A and of the eigenvector matrix (equations
+ *     (8) and (10) with the rotations of a step grouped); the workgroups
+ *     exchange tiles through memory once per block step (PCA_JACOBI_BLOCK;
+ *     the default from 224 bands). Every index pair is still rotated once per
+ *     sweep; only the order differs. It spreads one call over up to 32 CUs
+ *     and needs them all resident at once, so it pays when the call has the
+ *     GPU to itself; a workgroup that waits about half a second for the
+ *     others gives up and the call reports non-finite output.
+ * Rotation angles use equations (2)-(5) with (7) in the cancellation-free
+ * form; the flag PCA_JACOBI_FP64_ANGLES evaluates them (and the diagonal) in
+ * float64. A rotation is skipped when |a_pq| <= 2^-24 sqrt(|a_pp a_qq|) or
+ * |a_pq| <= 2^-24 ||C||_F / n_bands. Stops before a sweep when
  * off(A)/||C||_F <= tol, after a sweep that applied no rotation, or after
  * max_sweeps sweeps.
  * Eigenvalues are sorted in descending order (stable), eigenvector columns
@@ -186,13 +204,13 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
  *   eigvals  [n_bands] float32 out, descending.
  *   V        [n_bands][n_bands] float32 out; column j is eigenvector j.
  *   info     device pca_info out (may be NULL).
- *   flags    OR of pca_jacobi_flag values (other bits: PCA_ERR_ARG).
+ *   flags    OR of pca_jacobi_flag values (other bits, or both form flags:
+ *            PCA_ERR_ARG). PCA_JACOBI_OVERLAP_REPLAY applies to the
+ *            one-workgroup form only.
  *   ws       workspace of pca_workspace_size(PCA_OP_JACOBI, ..., max_sweeps).
- *            The first call with PCA_JACOBI_OVERLAP_REPLAY on a workspace
- *            needs it zero-filled (once, at allocation: its rotation log is
- *            read while it is written, and every call leaves the log zeroed
- *            for the next); calls that share a workspace must not overlap in
- *            time.
+ *            Its contents before the call do not matter (every call clears
+ *            what it reads before reading it); calls that share a workspace
+ *            must not overlap in time.
  */
 pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t max_sweeps,
                            int32_t flags, float *eigvals, float *V, pca_info *info,

@@ -16,6 +16,9 @@ from ._lib import (  # noqa: F401
     PCA_IN_U16_BSQ,
     PCA_JACOBI_FP64_ANGLES,
     PCA_JACOBI_OVERLAP_REPLAY,
+    PCA_JACOBI_ONE_CU,
+    PCA_JACOBI_BLOCK,
+    JACOBI_FORMS,
     PCA_OP_CENTER,
     PCA_OP_COVARIANCE,
     PCA_OP_JACOBI,

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libpca.so")
 PCA_OK, PCA_ERR_ARG, PCA_ERR_UNSUPPORTED, PCA_ERR_WORKSPACE, PCA_ERR_HIP = range(5)
 PCA_IN_F32, PCA_IN_U16, PCA_IN_F32_BSQ, PCA_IN_U16_BSQ = 0, 1, 2, 3
 PCA_COV_F32, PCA_COV_BF16X3, PCA_COV_BF16X4 = 0, 1, 2
-PCA_JACOBI_FP64_ANGLES, PCA_JACOBI_OVERLAP_REPLAY = 1, 2
+PCA_JACOBI_FP64_ANGLES, PCA_JACOBI_OVERLAP_REPLAY, PCA_JACOBI_ONE_CU, PCA_JACOBI_BLOCK = 1, 2, 4, 8
+JACOBI_FORMS = {"auto": 0, "one_cu": PCA_JACOBI_ONE_CU, "block": PCA_JACOBI_BLOCK}
 PCA_OP_CENTER, PCA_OP_COVARIANCE, PCA_OP_JACOBI, PCA_OP_PROJECT, PCA_OP_BACKWARD = range(5)
 
 COV_MODES = {"f32": PCA_COV_F32, "bf16x3": PCA_COV_BF16X3, "bf16x4": PCA_COV_BF16X4}
@@ -141,8 +142,8 @@ def pca_workspace_size(op: int, n_pixels: int, n_bands: int, k: int = 1, mode: i
 
 def workspace(nbytes: int, device=None) -> torch.Tensor:
     """A zero-filled device byte buffer for a workspace argument (torch
-    allocations are at least 256-byte aligned; the Jacobi call's overlapped
-    replay wants its workspace zero-filled before first use)."""
+    allocations are at least 256-byte aligned; no call depends on what a
+    workspace holds before it)."""
     return torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
 
 
@@ -165,13 +166,16 @@ def pca_covariance(Y, C, mean=None, mode: int = PCA_COV_F32, input_is_centered: 
 
 
 def pca_jacobi_eigh(C, eigvals, V, tol: float, max_sweeps: int, fp64_angles: bool = True, info=None, ws=None,
-                    overlap: bool = False):
-    """overlap: PCA_JACOBI_OVERLAP_REPLAY (eigenvectors formed while the
-    sweeps run; bitwise the same results)."""
+                    overlap: bool = False, form: str = "auto"):
+    """overlap: PCA_JACOBI_OVERLAP_REPLAY (one-workgroup form: eigenvectors
+    formed while the sweeps run; bitwise the same results). form: "auto"
+    (the library's choice by band count), "one_cu" (PCA_JACOBI_ONE_CU) or
+    "block" (PCA_JACOBI_BLOCK)."""
     m = C.shape[0]
     if ws is None:
         ws = workspace(pca_workspace_size(PCA_OP_JACOBI, 2, m, max_sweeps=max_sweeps), C.device)
-    flags = (PCA_JACOBI_FP64_ANGLES if fp64_angles else 0) | (PCA_JACOBI_OVERLAP_REPLAY if overlap else 0)
+    flags = ((PCA_JACOBI_FP64_ANGLES if fp64_angles else 0) | (PCA_JACOBI_OVERLAP_REPLAY if overlap else 0)
+             | JACOBI_FORMS[form])
     _check("pca_jacobi_eigh", _lib().pca_jacobi_eigh(_ptr(C), m, float(tol), int(max_sweeps), flags,
                                                      _ptr(eigvals), _ptr(V), _ptr(info), _ptr(ws), ws.numel(),
                                                      _stream()))

@@ -33,17 +33,23 @@ class PCAPipeline:
 
     def __init__(self, n_pixels: int, n_bands: int, k: int, mode: str = "f32",
                  tol: float = DEFAULT_TOL, max_sweeps: int = DEFAULT_MAX_SWEEPS,
-                 fp64_angles: bool = True, device="cuda", layout: str = "bip", overlap_replay: bool = True):
+                 fp64_angles: bool = True, device="cuda", layout: str = "bip", overlap_replay: bool = True,
+                 jacobi: str = "auto"):
         """layout: "bip" for [pixels, bands] cubes, "bsq" for [bands, pixels]
-        (band-sequential) cubes. overlap_replay: form the eigenvectors while
-        the Jacobi sweeps run, on other CUs of the same launch (for a cube
-        that has the GPU to itself; a stream of cubes leaves those CUs to
-        the other cubes' passes)."""
+        (band-sequential) cubes. overlap_replay: with the one-workgroup
+        Jacobi, form the eigenvectors while the sweeps run, on other CUs of
+        the same launch (for a cube that has the GPU to itself; a stream of
+        cubes leaves those CUs to the other cubes' passes). jacobi: "auto"
+        (block-cyclic on many CUs from 224 bands, one workgroup below),
+        "block" or "one_cu"."""
         self.n, self.m, self.k = int(n_pixels), int(n_bands), int(k)
         self.layout = layout
         self.mode = L.COV_MODES[mode] if isinstance(mode, str) else int(mode)
         self.tol, self.max_sweeps, self.fp64_angles = float(tol), int(max_sweeps), bool(fp64_angles)
         self.overlap_replay = bool(overlap_replay)
+        if jacobi not in L.JACOBI_FORMS:
+            raise ValueError(f"jacobi must be one of {sorted(L.JACOBI_FORMS)}")
+        self.jacobi = jacobi
         dev = torch.device(device)
         f32 = dict(dtype=torch.float32, device=dev)
         self.mean = torch.empty(self.m, **f32)
@@ -61,7 +67,7 @@ class PCAPipeline:
 
     def eigh(self):
         L.pca_jacobi_eigh(self.C, self.eigvals, self.V, self.tol, self.max_sweeps, self.fp64_angles,
-                          self.info, self.ws_jac, overlap=self.overlap_replay)
+                          self.info, self.ws_jac, overlap=self.overlap_replay, form=self.jacobi)
 
     def project(self, Y):
         L.pca_project(Y, self.mean, self.V, self.k, self.Q, layout=self.layout)
@@ -94,13 +100,18 @@ class PCAStream:
 
     def __init__(self, n_pixels: int, n_bands: int, k: int, mode: str = "f32", depth: int = 4,
                  tol: float = DEFAULT_TOL, max_sweeps: int = DEFAULT_MAX_SWEEPS,
-                 fp64_angles: bool = True, device="cuda", chain: bool = True, overlap_replay: bool = False):
+                 fp64_angles: bool = True, device="cuda", chain: bool = True, overlap_replay: bool = False,
+                 jacobi: str = "one_cu"):
+        """jacobi: the eigen-solver form of every cube (default the
+        one-workgroup form: the block-cyclic form spreads one cube over many
+        CUs and waits on all of them at every step, which pays only when the
+        cube has the GPU to itself)."""
         if depth < 1:
             raise ValueError("depth must be >= 1")
         self.depth = int(depth)
         self.chain = bool(chain)
         self.pipes = [PCAPipeline(n_pixels, n_bands, k, mode, tol, max_sweeps, fp64_angles, device,
-                                  overlap_replay=overlap_replay) for _ in range(self.depth)]
+                                  overlap_replay=overlap_replay, jacobi=jacobi) for _ in range(self.depth)]
         self.streams = [torch.cuda.Stream(device=device) for _ in range(self.depth)]
         self.events = [torch.cuda.Event() for _ in range(self.depth)]
         self.cov_done = [torch.cuda.Event() for _ in range(self.depth)]

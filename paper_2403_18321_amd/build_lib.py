@@ -28,7 +28,8 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-function"]
 
-SOURCES = ["capi.cpp", "center.hip", "covariance.hip", "jacobi.hip", "project.hip", "backward.hip", "batched.hip"]
+SOURCES = ["capi.cpp", "center.hip", "covariance.hip", "jacobi.hip", "jacobi_block.hip", "project.hip", "backward.hip",
+           "batched.hip"]
 
 
 def hipcc() -> str:

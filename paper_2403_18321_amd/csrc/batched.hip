@@ -66,6 +66,8 @@ __global__ __launch_bounds__(kSetupThreads) void batch_setup_kernel(const pca_cu
         a += batch_al(c.cov.bytes_sum);
         c.partShift = reinterpret_cast<float *>(a);
         a += batch_al(c.cov.bytes_shift);
+        c.srow = reinterpret_cast<float *>(a);
+        a += batch_al(c.cov.bytes_srow);
         c.part2 = reinterpret_cast<double *>(a);
         a += batch_al(c.cov.bytes_part2);
         c.C = reinterpret_cast<float *>(a);

@@ -29,10 +29,13 @@ inline pca_status check_cube(const void *Y, int dt, int64_t n, int32_t m, int64_
 inline pca_status hip_status(hipError_t e) { return e == hipSuccess ? PCA_OK : PCA_ERR_HIP; }
 
 size_t center_ws(const pca::CovPlan &p, int m) { return al(p.bytes_sum) + al((size_t)m * sizeof(double)); }
-size_t cov_ws(const pca::CovPlan &p) { return al(p.bytes_S) + al(p.bytes_sum) + al(p.bytes_shift) + al(p.bytes_part2); }
+size_t cov_ws(const pca::CovPlan &p)
+{
+    return al(p.bytes_S) + al(p.bytes_sum) + al(p.bytes_shift) + al(p.bytes_part2) + al(p.bytes_srow);
+}
 size_t jac_ws(const pca::JacPlan &p)
 {
-    return al(p.bytes_log) + al(p.bytes_lam) + al(p.bytes_vu) + al(p.bytes_info);
+    return al(p.bytes_log) + al(p.bytes_lam) + al(p.bytes_vu) + al(p.bytes_info) + al(p.bytes_block);
 }
 size_t bwd_ws(const pca::BwdPlan &p) { return al(p.bytes_part) + al(p.bytes_w) + al(p.bytes_sums) + al(p.bytes_g); }
 
@@ -153,9 +156,12 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
     double *partSum = reinterpret_cast<double *>(w + al(plan.bytes_S));
     float *partShift = reinterpret_cast<float *>(w + al(plan.bytes_S) + al(plan.bytes_sum));
     double *part2 = reinterpret_cast<double *>(w + al(plan.bytes_S) + al(plan.bytes_sum) + al(plan.bytes_shift));
+    float *srow = reinterpret_cast<float *>(w + al(plan.bytes_S) + al(plan.bytes_sum) + al(plan.bytes_shift) +
+                                            al(plan.bytes_part2));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (pca::launch_cov_shift(Y, dt, n_pixels, n_bands, ld_y, plan, srow, st) != hipSuccess) return PCA_ERR_HIP;
     hipError_t e = pca::launch_cov_partial(Y, dt, n_pixels, n_bands, ld_y, input_is_centered, mode, plan, partS,
-                                           partSum, partShift, st);
+                                           partSum, partShift, srow, st);
     if (e != hipSuccess) return PCA_ERR_HIP;
     return hip_status(pca::launch_cov_finalize(n_pixels, n_bands, input_is_centered, plan, partS, partSum,
                                                partShift, part2, C, mean, st));
@@ -167,7 +173,9 @@ pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t 
     if (!C || !eigvals || !V || !ws) return PCA_ERR_ARG;
     if (n_bands < 2 || n_bands > pca::kMaxBands) return PCA_ERR_ARG;
     if (!(tol >= 0.0) || !isfinite(tol) || max_sweeps < 0 || max_sweeps > 100000) return PCA_ERR_ARG;
-    if (flags & ~(PCA_JACOBI_FP64_ANGLES | PCA_JACOBI_OVERLAP_REPLAY)) return PCA_ERR_ARG;
+    if (flags & ~(PCA_JACOBI_FP64_ANGLES | PCA_JACOBI_OVERLAP_REPLAY | PCA_JACOBI_ONE_CU | PCA_JACOBI_BLOCK))
+        return PCA_ERR_ARG;
+    if ((flags & PCA_JACOBI_ONE_CU) && (flags & PCA_JACOBI_BLOCK)) return PCA_ERR_ARG;
     if (!aligned(ws, kWsAlign) || !aligned(C, 4) || !aligned(eigvals, 4) || !aligned(V, 4)) return PCA_ERR_ARG;
     if (info && !aligned(info, 8)) return PCA_ERR_ARG;
     const pca::JacPlan plan = pca::jac_plan(n_bands, max_sweeps);
@@ -180,9 +188,18 @@ pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t 
     float *Vu = reinterpret_cast<float *>(w);
     w += al(plan.bytes_vu);
     pca_info *info_ws = reinterpret_cast<pca_info *>(w);
-    return hip_status(pca::launch_jacobi(C, n_bands, tol, max_sweeps, flags & PCA_JACOBI_FP64_ANGLES,
-                                         (flags & PCA_JACOBI_OVERLAP_REPLAY) ? 1 : 0, plan, lam_u, rlog, Vu,
-                                         info_ws, eigvals, V, info, static_cast<hipStream_t>(stream)));
+    w += al(plan.bytes_info);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int fp64 = (flags & PCA_JACOBI_FP64_ANGLES) ? 1 : 0;
+    const bool block = (flags & PCA_JACOBI_BLOCK) || (!(flags & PCA_JACOBI_ONE_CU) && n_bands >= pca::kBjMinBands);
+    if (block) {
+        if (pca::launch_jacobi_block(C, n_bands, tol, max_sweeps, fp64, w, lam_u, Vu, plan.me, info_ws, st) !=
+            hipSuccess)
+            return PCA_ERR_HIP;
+        return hip_status(pca::launch_sort_sign(n_bands, plan.me, lam_u, Vu, info_ws, eigvals, V, info, st));
+    }
+    return hip_status(pca::launch_jacobi(C, n_bands, tol, max_sweeps, fp64, (flags & PCA_JACOBI_OVERLAP_REPLAY) ? 1 : 0,
+                                         plan, lam_u, rlog, Vu, info_ws, eigvals, V, info, st));
 }
 
 pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,

@@ -2,8 +2,9 @@
 // normalised by PIXELS - 1 as in Code 4.3), with the band-mean removal
 // (Algorithm 1, line 2) fused so that the cube is streamed from HBM once.
 //
+// Pass 0 (cov_shift): a shift row s, the mean of a sample of pixels per band.
 // Pass 1 (cov_partial): one workgroup per chunk of pixels. Each chunk is
-// shifted by its own first pixel s_w, and the workgroup accumulates on chip
+// shifted by s_w = s, and the workgroup accumulates on chip
 //   S_w = sum_{p in w} (y_p - s_w)(y_p - s_w)^T   (upper-triangle 32x32 blocks)
 //   t_w = sum_{p in w} (y_p - s_w)               (float64 per band)
 // with MFMA: float32 products (v_mfma_f32_32x32x2_f32) or the split-bfloat16
@@ -70,6 +71,74 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
     lo = (__bf16)(x - (float)hi);
 }
 
+// ---- pass 0: the shift row ------------------------------------------------
+//
+// s_b = mean of a sample of the pixels of band b: every pixel up to
+// kShiftSample of them, else kShiftRuns runs of 32 consecutive pixels spread
+// evenly over the cube, added in float64 in a fixed order. Any shift gives
+// the same covariance in exact arithmetic (pass 2 removes it exactly); one
+// close to the band mean keeps the shifted values small whatever a single
+// pixel holds (a dead or hot detector column at the start of every chunk,
+// for one), and with them the rounding of the products, which the
+// split-bfloat16 forms feel most. uint16 cubes round s to an integer so that
+// the row can also be held in the cube's own type; float32 cubes keep it as
+// it is. Shift area: float32 s[256], then the cube-type row [256].
+constexpr int kShiftRuns = 32;
+constexpr int kShiftSample = 32 * kShiftRuns;   // 1024 pixels
+constexpr int kShiftThreads = 256;              // one 32-band block a workgroup
+
+__device__ inline int64_t shift_pixel(int64_t n, int i)
+{
+    return n <= kShiftSample ? (int64_t)i : (int64_t)(i >> 5) * n / kShiftRuns + (i & 31);
+}
+
+// Band block bb (bands 32 bb .. 32 bb + 31) of the shift row. Band-interleaved
+// cubes: the 32 lanes of a group read one sampled pixel's 32 bands;
+// band-sequential cubes: 8 lanes read 8 consecutive sampled pixels of a band.
+template <typename T>
+__device__ void cov_shift_body(const T *__restrict__ Y, int64_t n, int m, int64_t ld, bool bsq, int bb,
+                               float *__restrict__ srow)
+{
+    __shared__ double red[32][9];
+    const int tid = threadIdx.x;
+    const int ns = n < kShiftSample ? (int)n : kShiftSample;
+    const int bl = bsq ? tid >> 3 : tid & 31;
+    const int i0 = bsq ? tid & 7 : tid >> 5;
+    const int b = 32 * bb + bl;
+    double a = 0.0;
+    if (b < m) {
+        const T *base = bsq ? Y + (int64_t)b * ld : Y + b;
+        const int64_t step = bsq ? 1 : ld;
+#pragma unroll 8
+        for (int i = i0; i < ns; i += 8) a += (double)load_elem(base + shift_pixel(n, i) * step);
+    }
+    red[bl][i0] = a;
+    __syncthreads();
+    if (tid < 32) {
+        const int bq = 32 * bb + tid;
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += red[tid][q];
+        T *rowT = reinterpret_cast<T *>(srow + 256);
+        float sv = 0.f;
+        if (bq < m) {
+            const double mean = t / (double)ns;
+            if constexpr (sizeof(T) == 2) sv = (float)fmin(fmax(rint(mean), 0.0), 65535.0);
+            else sv = (float)mean;
+        }
+        srow[bq] = sv;
+        if constexpr (sizeof(T) == 2) rowT[bq] = (T)(unsigned)sv;
+        else rowT[bq] = sv;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kShiftThreads) void cov_shift_kernel(const T *__restrict__ Y, int64_t n, int m,
+                                                                  int64_t ld, int bsq, float *__restrict__ srow)
+{
+    cov_shift_body<T>(Y, n, m, ld, bsq != 0, (int)blockIdx.x, srow);
+}
+
 // One chunk c of one cube (the body of the single-cube and the batched
 // launches). kSkip: products of slots past the cube's last block are skipped
 // (the batched launch sizes S for the widest cube of any batch).
@@ -77,7 +146,7 @@ template <typename T, int VEC, int MODE, int S, bool kSkip = false>
 __device__ __forceinline__ void cov_partial_body(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
     int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
-    int64_t c)
+    const float *__restrict__ srow, int64_t c)
 {
     constexpr int kF32Max = KT * (256 + 32);
     constexpr int kBfMax = 256 * kBfPitch;
@@ -93,13 +162,13 @@ __device__ __forceinline__ void cov_partial_body(
     const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
     const int pf = f32_pitch(mpad);
 
-    // Shift of this chunk: its first pixel (zero when the cube is centred).
+    // Shift: the cube's shift row (zero when the cube is centred).
     float shift[4];
     double sums[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int b = slot_band<VEC>(lane, s);
-        shift[s] = (!centered && b < m) ? load_elem(Y + pbeg * ld + b) : 0.f;
+        shift[s] = (!centered && b < m) ? srow[b] : 0.f;
         sums[s] = 0.0;
     }
 
@@ -287,9 +356,10 @@ __device__ __forceinline__ void cov_partial_body(
 template <typename T, int VEC, int MODE, int S>
 __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int centered, int64_t chunk, int nb,
-    int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+    int nblk, int mpad, float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
+    const float *__restrict__ srow)
 {
-    cov_partial_body<T, VEC, MODE, S>(Y, n, m, ld, centered, chunk, nb, nblk, mpad, partS, partSum, partShift,
+    cov_partial_body<T, VEC, MODE, S>(Y, n, m, ld, centered, chunk, nb, nblk, mpad, partS, partSum, partShift, srow,
                                       (int64_t)blockIdx.x);
 }
 
@@ -305,9 +375,9 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
 //    barriers are explicit;
 //  * 8 waves of modest register use, two per SIMD, so that one wave's
 //    centring and splitting overlaps another's matrix products;
-//  * the chunk shift is always the chunk's first pixel; rows past the chunk
-//    end, and lanes past the last band, copy that pixel's values, so they
-//    centre to exact zeros without masks.
+//  * rows past the chunk end, and lanes past the last band, copy the shift
+//    row (held in the cube's own type after the float32 row), so they centre
+//    to exact zeros without masks.
 constexpr int kRing = 3;
 constexpr int kDmaWaves = 8;
 constexpr int kDmaThreads = 64 * kDmaWaves;
@@ -344,7 +414,8 @@ typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 template <typename T, int MODE, int S>
 __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
-    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
+    const float *__restrict__ srow)
 {
     // Staged pixel rows of 256 elements (288 floats for the float32 products
     // of a float32 cube, whose two half-waves read rows one apart). A copy
@@ -375,7 +446,7 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     const int64_t nst = (pend - pbeg + KT - 1) / KT;
     const int cl = kU16 ? (lane & 31) : lane;                  // lane within its row
     const int loff = kPerLane * cl < m ? kPerLane * cl : 0;   // m % kPerLane == 0 on this path
-    const T *row0 = Y + pbeg * ld;
+    const T *row0 = reinterpret_cast<const T *>(srow + 256);   // the shift row in the cube's type
 
     // Workgroups walk their chunks from different starting stages (evenly
     // spread over the chunk, wrapping around): chunks are equal power-of-two
@@ -399,8 +470,8 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
         }
     };
 
-    // Shift per band: the first pixel; bands past the last one take the
-    // values their lanes copy (row0[b mod kPerLane]), so they centre to zero.
+    // Shift per band: the shift row; bands past the last one take the values
+    // their lanes copy (row0[b mod kPerLane]), so they centre to zero.
     for (int b = tid; b < 256; b += kDmaThreads) shv[b] = load_elem(row0 + (b < m ? b : b % kPerLane));
     asm volatile("" ::: "memory");   // the shift load and store stay ahead of the copies
     issue(raw0, 0);
@@ -590,7 +661,8 @@ constexpr int kBsqPitchF = 34;
 template <typename T, int MODE, int S>
 __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad, int idbase,
-    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
+    const float *__restrict__ srow)
 {
     constexpr int kHalf = 256 * kBfPitch;
     __shared__ __attribute__((aligned(16))) float tileF[MODE == MODE_F32 ? 256 * kBsqPitchF : 4];
@@ -606,13 +678,13 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
     const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
     const int64_t nst = (pend - pbeg + KT - 1) / KT;
 
-    // Shift: the chunk's first pixel, per band.
+    // Shift: the cube's shift row, per band.
     float sh[8];
     double sums[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int b = bg + 32 * j;
-        sh[j] = b < m ? load_elem(Y + (int64_t)b * ld + pbeg) : 0.f;
+        sh[j] = b < m ? srow[b] : 0.f;
         sums[j] = 0.0;
     }
 
@@ -764,7 +836,8 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
 template <typename T, int MODE, int S>
 __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
-    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift)
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
+    const float *__restrict__ srow)
 {
     static_assert(MODE != MODE_F32, "split forms only");
     constexpr int kPix = 16 / (int)sizeof(T);        // pixels per lane and copy
@@ -799,7 +872,7 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int b = bg + 32 * j;
-        sh[j] = b < m ? load_elem(Y + (int64_t)b * ld + pbeg) : 0.f;
+        sh[j] = b < m ? srow[b] : 0.f;
         sums[j] = 0.0;
     }
     asm volatile("" ::: "memory");   // the shift loads stay ahead of the copies
@@ -1074,6 +1147,16 @@ __device__ inline int batch_find(const BatchCube *t, int nc, int64_t item)
 // Persistent: workgroups take (cube, chunk) items from a queue until it is
 // empty; each item's results land in fixed slots, so the order in which
 // items are taken does not change them.
+// Shift rows of every cube of a batch: workgroup (bb, r) takes band block bb
+// of the cube at table position r.
+template <typename T>
+__global__ __launch_bounds__(kShiftThreads) void cov_shift_batched_kernel(const char *ws)
+{
+    const BatchCube &cb = batch_table(ws)[blockIdx.y];
+    if ((int)blockIdx.x >= cb.cov.nb) return;
+    cov_shift_body<T>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, false, (int)blockIdx.x, cb.srow);
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void cov_partial_batched_kernel(char *ws, int nc, int64_t total)
 {
@@ -1089,7 +1172,7 @@ __global__ __launch_bounds__(kThreads) void cov_partial_batched_kernel(char *ws,
         const BatchCube &cb = t[batch_find<&BatchCube::w_cov>(t, nc, item)];
         cov_partial_body<T, 1, MODE, kMaxSlots, true>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, 0,
                                                       cb.cov.chunk, cb.cov.nb, cb.cov.nblk, cb.cov.mpad, cb.partS,
-                                                      cb.partSum, cb.partShift, item - cb.w_cov);
+                                                      cb.partSum, cb.partShift, cb.srow, item - cb.w_cov);
     }
 }
 
@@ -1115,25 +1198,25 @@ __global__ __launch_bounds__(1024) void cov_finalize_sum_batched_kernel(const ch
 
 template <typename T, int VEC, int MODE>
 hipError_t launch_partial_m(const T *Y, int64_t n, int m, int64_t ld, int centered, const CovPlan &p,
-                            float *partS, double *partSum, float *partShift, hipStream_t st)
+                            float *partS, double *partSum, float *partShift, const float *srow, hipStream_t st)
 {
     dim3 grid((unsigned)p.nchunks), block(kThreads);
     switch (cov_slots(p.nb)) {
     case 3:
         hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE, 3>), grid, block, 0, st, Y, n, m, ld, centered, p.chunk,
-                           p.nb, p.nblk, p.mpad, partS, partSum, partShift);
+                           p.nb, p.nblk, p.mpad, partS, partSum, partShift, srow);
         break;
     case 6:
         hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE, 6>), grid, block, 0, st, Y, n, m, ld, centered, p.chunk,
-                           p.nb, p.nblk, p.mpad, partS, partSum, partShift);
+                           p.nb, p.nblk, p.mpad, partS, partSum, partShift, srow);
         break;
     case 7:
         hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE, 7>), grid, block, 0, st, Y, n, m, ld, centered, p.chunk,
-                           p.nb, p.nblk, p.mpad, partS, partSum, partShift);
+                           p.nb, p.nblk, p.mpad, partS, partSum, partShift, srow);
         break;
     default:
         hipLaunchKernelGGL((cov_partial_kernel<T, VEC, MODE, kMaxSlots>), grid, block, 0, st, Y, n, m, ld, centered,
-                           p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift);
+                           p.chunk, p.nb, p.nblk, p.mpad, partS, partSum, partShift, srow);
         break;
     }
     return hipGetLastError();
@@ -1141,25 +1224,25 @@ hipError_t launch_partial_m(const T *Y, int64_t n, int m, int64_t ld, int center
 
 template <typename T, int MODE>
 hipError_t launch_dma_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
-                        double *partSum, float *partShift, hipStream_t st)
+                        double *partSum, float *partShift, const float *srow, hipStream_t st)
 {
     dim3 grid((unsigned)p.nchunks), block(kDmaThreads);
     switch (dma_slots(p.nb)) {
     case 2:
         hipLaunchKernelGGL((cov_partial_dma_kernel<T, MODE, 2>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
-                           p.mpad, partS, partSum, partShift);
+                           p.mpad, partS, partSum, partShift, srow);
         break;
     case 3:
         hipLaunchKernelGGL((cov_partial_dma_kernel<T, MODE, 3>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
-                           p.mpad, partS, partSum, partShift);
+                           p.mpad, partS, partSum, partShift, srow);
         break;
     case 4:
         hipLaunchKernelGGL((cov_partial_dma_kernel<T, MODE, 4>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
-                           p.mpad, partS, partSum, partShift);
+                           p.mpad, partS, partSum, partShift, srow);
         break;
     default:
         hipLaunchKernelGGL((cov_partial_dma_kernel<T, MODE, 5>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk,
-                           p.mpad, partS, partSum, partShift);
+                           p.mpad, partS, partSum, partShift, srow);
         break;
     }
     return hipGetLastError();
@@ -1167,30 +1250,30 @@ hipError_t launch_dma_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan 
 
 template <typename T, int MODE, int S>
 void launch_bsq_s(const T *Y, int64_t n, int m, int64_t ld, const CovPlan &p, int idbase, float *partS,
-                  double *partSum, float *partShift, hipStream_t st)
+                  double *partSum, float *partShift, const float *srow, hipStream_t st)
 {
     hipLaunchKernelGGL((cov_partial_bsq_kernel<T, MODE, S>), dim3((unsigned)p.nchunks), dim3(kDmaThreads), 0, st, Y, n,
-                       m, ld, p.chunk, p.nb, p.nblk, p.mpad, idbase, partS, partSum, partShift);
+                       m, ld, p.chunk, p.nb, p.nblk, p.mpad, idbase, partS, partSum, partShift, srow);
 }
 
 template <typename T, int MODE>
 hipError_t launch_bsq_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS, double *partSum,
-                        float *partShift, hipStream_t st)
+                        float *partShift, const float *srow, hipStream_t st)
 {
     const int slots = dma_slots(p.nb);
     if (MODE == MODE_F32 && slots > 3) {
         for (int base = 0; base < p.nblk; base += 3 * kDmaWaves)
-            launch_bsq_s<T, MODE, 3>(Y, n, m, ld, p, base, partS, partSum, partShift, st);
+            launch_bsq_s<T, MODE, 3>(Y, n, m, ld, p, base, partS, partSum, partShift, srow, st);
         return hipGetLastError();
     }
     switch (slots) {
-    case 2: launch_bsq_s<T, MODE, 2>(Y, n, m, ld, p, 0, partS, partSum, partShift, st); break;
-    case 3: launch_bsq_s<T, MODE, 3>(Y, n, m, ld, p, 0, partS, partSum, partShift, st); break;
+    case 2: launch_bsq_s<T, MODE, 2>(Y, n, m, ld, p, 0, partS, partSum, partShift, srow, st); break;
+    case 3: launch_bsq_s<T, MODE, 3>(Y, n, m, ld, p, 0, partS, partSum, partShift, srow, st); break;
     case 4:
-        if constexpr (MODE != MODE_F32) launch_bsq_s<T, MODE, 4>(Y, n, m, ld, p, 0, partS, partSum, partShift, st);
+        if constexpr (MODE != MODE_F32) launch_bsq_s<T, MODE, 4>(Y, n, m, ld, p, 0, partS, partSum, partShift, srow, st);
         break;
     default:
-        if constexpr (MODE != MODE_F32) launch_bsq_s<T, MODE, 5>(Y, n, m, ld, p, 0, partS, partSum, partShift, st);
+        if constexpr (MODE != MODE_F32) launch_bsq_s<T, MODE, 5>(Y, n, m, ld, p, 0, partS, partSum, partShift, srow, st);
         break;
     }
     return hipGetLastError();
@@ -1198,12 +1281,12 @@ hipError_t launch_bsq_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan 
 
 template <typename T, int MODE>
 hipError_t launch_bsq_dma_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
-                            double *partSum, float *partShift, hipStream_t st)
+                            double *partSum, float *partShift, const float *srow, hipStream_t st)
 {
     const dim3 grid((unsigned)p.nchunks), block(kDmaThreads);
 #define PCA_BSQ_DMA(S)                                                                                             \
     hipLaunchKernelGGL((cov_partial_bsq_dma_kernel<T, MODE, S>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb,   \
-                       p.nblk, p.mpad, partS, partSum, partShift)
+                       p.nblk, p.mpad, partS, partSum, partShift, srow)
     switch (dma_slots(p.nb)) {
     case 2: PCA_BSQ_DMA(2); break;
     case 3: PCA_BSQ_DMA(3); break;
@@ -1224,27 +1307,27 @@ inline bool bsq_dma_ok(const void *Y, int elem_bytes, int mode, int64_t n, int64
 
 template <typename T>
 hipError_t launch_partial_bsq(const T *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p, float *partS,
-                              double *partSum, float *partShift, hipStream_t st)
+                              double *partSum, float *partShift, const float *srow, hipStream_t st)
 {
     if (bsq_dma_ok(Y, (int)sizeof(T), mode, n, ld)) {
-        if (mode == MODE_BF16X3) return launch_bsq_dma_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
-        return launch_bsq_dma_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
+        if (mode == MODE_BF16X3) return launch_bsq_dma_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
+        return launch_bsq_dma_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     }
     switch (mode) {
-    case MODE_F32: return launch_bsq_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, st);
-    case MODE_BF16X3: return launch_bsq_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
-    default: return launch_bsq_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    case MODE_F32: return launch_bsq_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
+    case MODE_BF16X3: return launch_bsq_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
+    default: return launch_bsq_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     }
 }
 
 template <typename T>
 hipError_t launch_partial_dma(const T *Y, int64_t n, int m, int64_t ld, int mode, const CovPlan &p,
-                              float *partS, double *partSum, float *partShift, hipStream_t st)
+                              float *partS, double *partSum, float *partShift, const float *srow, hipStream_t st)
 {
     switch (mode) {
-    case MODE_F32: return launch_dma_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, st);
-    case MODE_BF16X3: return launch_dma_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, st);
-    default: return launch_dma_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, st);
+    case MODE_F32: return launch_dma_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
+    case MODE_BF16X3: return launch_dma_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
+    default: return launch_dma_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     }
 }
 
@@ -1258,15 +1341,15 @@ inline bool dma_ok(const void *Y, int dt, int m, int64_t ld)
 
 template <typename T, int VEC>
 hipError_t launch_partial_t(const T *Y, int64_t n, int m, int64_t ld, int centered, int mode,
-                            const CovPlan &p, float *partS, double *partSum, float *partShift, hipStream_t st)
+                            const CovPlan &p, float *partS, double *partSum, float *partShift, const float *srow, hipStream_t st)
 {
     switch (mode) {
     case MODE_F32:
-        return launch_partial_m<T, VEC, MODE_F32>(Y, n, m, ld, centered, p, partS, partSum, partShift, st);
+        return launch_partial_m<T, VEC, MODE_F32>(Y, n, m, ld, centered, p, partS, partSum, partShift, srow, st);
     case MODE_BF16X3:
-        return launch_partial_m<T, VEC, MODE_BF16X3>(Y, n, m, ld, centered, p, partS, partSum, partShift, st);
+        return launch_partial_m<T, VEC, MODE_BF16X3>(Y, n, m, ld, centered, p, partS, partSum, partShift, srow, st);
     default:
-        return launch_partial_m<T, VEC, MODE_BF16X4>(Y, n, m, ld, centered, p, partS, partSum, partShift, st);
+        return launch_partial_m<T, VEC, MODE_BF16X4>(Y, n, m, ld, centered, p, partS, partSum, partShift, srow, st);
     }
 }
 
@@ -1274,49 +1357,50 @@ hipError_t launch_partial_t(const T *Y, int64_t n, int m, int64_t ld, int center
 
 CovPlan cov_plan(int64_t n, int m)
 {
-    CovPlan p;
     int64_t target = (n + kCovTargetChunks - 1) / kCovTargetChunks;
     target = (target + KT - 1) / KT * KT;
-    if (target < KT) target = KT;
-    if (target > kCovMaxChunk) target = kCovMaxChunk;
-    p.chunk = target;
-    p.nchunks = (n + p.chunk - 1) / p.chunk;
-    p.mpad = round_up(m, 32);
-    p.nb = p.mpad / 32;
-    p.nblk = p.nb * (p.nb + 1) / 2;
-    p.bytes_S = (size_t)p.nchunks * p.nblk * 1024 * sizeof(float);
-    p.bytes_sum = (size_t)p.nchunks * p.mpad * sizeof(double);
-    p.bytes_shift = (size_t)p.nchunks * p.mpad * sizeof(float);
-    p.groups = (int)(p.nchunks < 8 ? p.nchunks : 8);
-    p.bytes_part2 = ((size_t)p.groups * p.nblk * 1024 + 1 + 256) * sizeof(double);
-    return p;
+    return cov_plan_chunk(n, m, target < KT ? KT : target);
+}
+
+hipError_t launch_cov_shift(const void *Y, int dt, int64_t n, int m, int64_t ld, const CovPlan &plan, float *srow,
+                            hipStream_t st)
+{
+    const dim3 grid((unsigned)plan.nb), block(kShiftThreads);
+    const int bsq = (dt == PCA_IN_F32_BSQ || dt == PCA_IN_U16_BSQ) ? 1 : 0;
+    if (dt == PCA_IN_F32 || dt == PCA_IN_F32_BSQ)
+        hipLaunchKernelGGL(cov_shift_kernel<float>, grid, block, 0, st, static_cast<const float *>(Y), n, m, ld, bsq,
+                           srow);
+    else
+        hipLaunchKernelGGL(cov_shift_kernel<uint16_t>, grid, block, 0, st, static_cast<const uint16_t *>(Y), n, m, ld,
+                           bsq, srow);
+    return hipGetLastError();
 }
 
 hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
                               int mode, const CovPlan &plan, float *partS, double *partSum,
-                              float *partShift, hipStream_t st)
+                              float *partShift, const float *srow, hipStream_t st)
 {
     if (dt == PCA_IN_F32_BSQ)
-        return launch_partial_bsq(static_cast<const float *>(Y), n, m, ld, mode, plan, partS, partSum, partShift, st);
+        return launch_partial_bsq(static_cast<const float *>(Y), n, m, ld, mode, plan, partS, partSum, partShift, srow, st);
     if (dt == PCA_IN_U16_BSQ)
         return launch_partial_bsq(static_cast<const uint16_t *>(Y), n, m, ld, mode, plan, partS, partSum, partShift,
-                                  st);
+                                  srow, st);
     if (dma_ok(Y, dt, m, ld)) {
         if (dt == PCA_IN_F32)
             return launch_partial_dma(static_cast<const float *>(Y), n, m, ld, mode, plan, partS, partSum, partShift,
-                                      st);
+                                      srow, st);
         return launch_partial_dma(static_cast<const uint16_t *>(Y), n, m, ld, mode, plan, partS, partSum, partShift,
-                                  st);
+                                  srow, st);
     }
     const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32) {
         const float *y = static_cast<const float *>(Y);
-        return v4 ? launch_partial_t<float, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st)
-                  : launch_partial_t<float, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st);
+        return v4 ? launch_partial_t<float, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, srow, st)
+                  : launch_partial_t<float, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, srow, st);
     }
     const uint16_t *y = static_cast<const uint16_t *>(Y);
-    return v4 ? launch_partial_t<uint16_t, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st)
-              : launch_partial_t<uint16_t, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, st);
+    return v4 ? launch_partial_t<uint16_t, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, srow, st)
+              : launch_partial_t<uint16_t, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, srow, st);
 }
 
 hipError_t launch_cov_finalize(int64_t n, int m, int centered, const CovPlan &plan, const float *partS,
@@ -1342,6 +1426,9 @@ hipError_t launch_cov_batched(int dt, int mode, const char *ws, const int64_t to
     if (g < 1) g = 1;
     char *w = const_cast<char *>(ws);
     const dim3 grid((unsigned)g), block(kThreads);
+    const dim3 sgrid(8u, (unsigned)n_cubes);
+    if (dt == PCA_IN_F32) hipLaunchKernelGGL(cov_shift_batched_kernel<float>, sgrid, dim3(kShiftThreads), 0, st, ws);
+    else hipLaunchKernelGGL(cov_shift_batched_kernel<uint16_t>, sgrid, dim3(kShiftThreads), 0, st, ws);
 #define PCA_COV_B(T, M)                                                                                           \
     hipLaunchKernelGGL((cov_partial_batched_kernel<T, M>), grid, block, 0, st, w, n_cubes, total[0])
     if (dt == PCA_IN_F32) {

@@ -52,8 +52,9 @@
 // so its first non-zero value is final), replays the steps before the first
 // end mark and stops there. Entries go through agent-scope coherent stores
 // and loads, which are visible across the chip's separate L2 caches without
-// cache flushes or fences. sort_sign_kernel, the next launch, zeroes the used
-// part of the log again. The Jacobi workgroup never waits for the followers,
+// cache flushes or fences. log_clear_kernel zeroes the whole log before the
+// launch, so nothing a previous call left in the workspace is ever read as an
+// entry. The Jacobi workgroup never waits for the followers,
 // and a follower that sees an entry stay zero for about a second writes NaN
 // rows and exits, so every workgroup ends.
 //
@@ -751,17 +752,8 @@ __global__ __launch_bounds__(kJThreads) void jacobi_follow_kernel(const float *_
 // sign from the column's largest-magnitude entry (lowest row on ties).
 __device__ __forceinline__ void sort_sign_body(int m, int n, const double *__restrict__ lam_u, const float *__restrict__ VuT,
                                       const pca_info *__restrict__ info_ws, float *__restrict__ eigvals,
-                                      float *__restrict__ V, pca_info *__restrict__ info_out, int wg, int nwg,
-                                      float2 *__restrict__ rlog_clear)
+                                      float *__restrict__ V, pca_info *__restrict__ info_out, int wg)
 {
-    // The launches that read the rotation log have ended: zero its used
-    // batches for the next call that reads it while it is written.
-    if (rlog_clear) {
-        const int64_t T = info_ws->steps;
-        const int64_t used = (T / kLogBatch + 1) * kLogBatch * (n / 2);
-        for (int64_t t = (int64_t)wg * blockDim.x + threadIdx.x; t < used; t += (int64_t)nwg * blockDim.x)
-            rlog_clear[t] = make_float2(0.f, 0.f);
-    }
     __shared__ int perm[256];
     __shared__ double lam[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -818,10 +810,9 @@ __global__ __launch_bounds__(256) void sort_sign_kernel(int m, int n, const doub
                                                         const float *__restrict__ VuT,
                                                         const pca_info *__restrict__ info_ws,
                                                         float *__restrict__ eigvals, float *__restrict__ V,
-                                                        pca_info *__restrict__ info_out,
-                                                        float2 *__restrict__ rlog_clear)
+                                                        pca_info *__restrict__ info_out)
 {
-    sort_sign_body(m, n, lam_u, VuT, info_ws, eigvals, V, info_out, (int)blockIdx.x, (int)gridDim.x, rlog_clear);
+    sort_sign_body(m, n, lam_u, VuT, info_ws, eigvals, V, info_out, (int)blockIdx.x);
 }
 
 // ---- batched form ------------------------------------------------------------
@@ -886,15 +877,28 @@ __global__ __launch_bounds__(256) void sort_sign_batched_kernel(const char *ws, 
     const int64_t item = blockIdx.x;
     const BatchCube &cb = t[jbatch_find<&BatchCube::w_sort>(t, nc, item)];
     sort_sign_body(cb.m, cb.m + (cb.m & 1), cb.lam_u, cb.Vu, cb.info_ws, cb.eigvals, cb.V, cb.info,
-                   (int)(item - cb.w_sort), (cb.m + 3) / 4, nullptr);
+                   (int)(item - cb.w_sort));
 }
 
+
+__global__ __launch_bounds__(256) void log_clear_kernel(float4 *p, int64_t n4)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
 
 template <int L>
 void launch_jac(const float *C, int m, int n, double tol, int max_sweeps, int fp64_angles, double *lam_u,
                 float2 *rlog, pca_info *info_ws, int overlap, float *Vu, hipStream_t st)
 {
     if (overlap) {
+        // The followers read the log while it is written and take the first
+        // non-zero value of an entry as final: clear the whole log first, so
+        // the call depends on nothing a previous call left in the workspace.
+        const JacPlan jp = jac_plan(m, max_sweeps);
+        const int64_t n4 = jp.log_steps * jp.npairs / 2;   // two entries per 16 bytes (log_steps is a multiple of 16)
+        const unsigned nclr = (unsigned)((n4 + 255) / 256 < 1024 ? (n4 + 255) / 256 : 1024);
+        hipLaunchKernelGGL(log_clear_kernel, dim3(nclr), dim3(256), 0, st, reinterpret_cast<float4 *>(rlog), n4);
         const int rows = follow_rows(n);
         const unsigned nf = (unsigned)((n + rows - 1) / rows);
         hipLaunchKernelGGL(jacobi_follow_kernel<L>, dim3(1 + nf), dim3(kJThreads), 0, st, C, m, n, tol, max_sweeps,
@@ -940,8 +944,15 @@ hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int 
                            (const pca_info *)info_ws, Vu);
     }
     hipLaunchKernelGGL(sort_sign_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, m, n,
-                       (const double *)lam_u, (const float *)Vu, (const pca_info *)info_ws, eigvals, V, info_out,
-                       rlog);
+                       (const double *)lam_u, (const float *)Vu, (const pca_info *)info_ws, eigvals, V, info_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_sign(int m, int n, const double *lam_u, const float *Vu, const pca_info *info_ws,
+                            float *eigvals, float *V, pca_info *info_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(sort_sign_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, m, n, lam_u, Vu, info_ws,
+                       eigvals, V, info_out);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct CovPlan {
     size_t bytes_shift;  // per-chunk shifts, float32
     int groups;          // chunk groups of the first finalize pass
     size_t bytes_part2;  // float64 partial results of those groups + means
+    size_t bytes_srow;   // shift row: float32 [256], then the same row in the cube's type [256]
 };
 CovPlan cov_plan(int64_t n, int m);
 
@@ -48,12 +49,16 @@ __host__ __device__ inline CovPlan cov_plan_chunk(int64_t n, int m, int64_t chun
     p.bytes_shift = (size_t)p.nchunks * p.mpad * sizeof(float);
     p.groups = (int)(p.nchunks < 8 ? p.nchunks : 8);
     p.bytes_part2 = ((size_t)p.groups * p.nblk * 1024 + 1 + 256) * sizeof(double);
+    p.bytes_srow = 2 * 256 * sizeof(float);
     return p;
 }
 
+// Pass 0: the shift row (written to srow, read by pass 1).
+hipError_t launch_cov_shift(const void *Y, int dt, int64_t n, int m, int64_t ld, const CovPlan &plan, float *srow,
+                            hipStream_t st);
 hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t ld, int centered,
                               int mode, const CovPlan &plan, float *partS, double *partSum,
-                              float *partShift, hipStream_t st);
+                              float *partShift, const float *srow, hipStream_t st);
 hipError_t launch_cov_finalize(int64_t n, int m, int centered, const CovPlan &plan, const float *partS,
                                const double *partSum, const float *partShift, double *part2, float *C,
                                float *mean, hipStream_t st);
@@ -72,7 +77,33 @@ struct JacPlan {
     size_t bytes_lam;    // unsorted eigenvalues, float64
     size_t bytes_vu;     // unsorted eigenvectors, float32 me x me
     size_t bytes_info;   // internal pca_info
+    size_t bytes_block;  // block-cyclic form: matrix tiles, U's, partial sums, step flags
 };
+
+// Block-cyclic Jacobi on many CUs (jacobi_block.hip): blocks of 16 indices
+// (an even number of them), one workgroup per (row block pair, column block
+// pair), P x P workgroups.
+constexpr int kBjBlock = 16;
+__host__ __device__ inline int bj_blocks(int m)
+{
+    int nb = (m + kBjBlock - 1) / kBjBlock;
+    nb += nb & 1;
+    return nb < 2 ? 2 : nb;
+}
+__host__ __device__ inline size_t bj_workspace_bytes(int m)
+{
+    const int nb = bj_blocks(m), P = nb / 2;
+    const size_t Mp = (size_t)nb * kBjBlock;
+    // H (float64, two steps), U (float64, two steps), V (float32), partial
+    // sums (two steps, 32 bytes per workgroup), step flags.
+    return 2 * Mp * Mp * sizeof(double) + 2 * (size_t)P * 1024 * sizeof(double) + Mp * Mp * sizeof(float) +
+           2 * (size_t)P * P * 32 + 256 * sizeof(unsigned int);
+}
+// Band counts from which pca_jacobi_eigh takes the block-cyclic form by default.
+constexpr int kBjMinBands = 224;
+// Workgroups of the block-cyclic form (all on one XCD) and column pairs each.
+constexpr int kBjMaxGroups = 32;
+constexpr int kBjMaxColPairs = 2;
 
 // The rotation log is read in batches of kLogBatch steps while it is written
 // (overlapped replay); its capacity covers the batch that holds the step
@@ -88,6 +119,7 @@ __host__ __device__ inline JacPlan jac_plan(int m, int max_sweeps)
     p.bytes_lam = (size_t)p.me * sizeof(double);
     p.bytes_vu = (size_t)p.me * p.me * sizeof(float);
     p.bytes_info = sizeof(pca_info);
+    p.bytes_block = bj_workspace_bytes(m);
     return p;
 }
 
@@ -126,6 +158,7 @@ struct BatchCube {
     float *partS;
     double *partSum;
     float *partShift;
+    float *srow;
     double *part2;
     float *C;
     float2 *rlog;
@@ -160,7 +193,8 @@ __host__ __device__ inline void batch_counts(const CovPlan &cp, int64_t n, int m
 // Workspace bytes of one cube (after the table).
 __host__ __device__ inline size_t batch_cube_bytes(const CovPlan &cp, const JacPlan &jp, int m)
 {
-    return batch_al(cp.bytes_S) + batch_al(cp.bytes_sum) + batch_al(cp.bytes_shift) + batch_al(cp.bytes_part2) +
+    return batch_al(cp.bytes_S) + batch_al(cp.bytes_sum) + batch_al(cp.bytes_shift) + batch_al(cp.bytes_srow) +
+           batch_al(cp.bytes_part2) +
            batch_al((size_t)m * m * sizeof(float)) + batch_al(jp.bytes_log) + batch_al(jp.bytes_lam) +
            batch_al(jp.bytes_vu) + batch_al(jp.bytes_info);
 }
@@ -202,6 +236,11 @@ hipError_t launch_jacobi(const float *C, int m, double tol, int max_sweeps, int 
                          const JacPlan &plan, double *lam_u, float2 *log, float *Vu,
                          pca_info *info_ws, float *eigvals, float *V, pca_info *info_out,
                          hipStream_t st);
+
+hipError_t launch_jacobi_block(const float *C, int m, double tol, int max_sweeps, int fp64_angles, char *ws,
+                               double *lam_u, float *VuT, int nvu, pca_info *info_ws, hipStream_t st);
+hipError_t launch_sort_sign(int m, int n, const double *lam_u, const float *Vu, const pca_info *info_ws,
+                            float *eigvals, float *V, pca_info *info_out, hipStream_t st);
 
 // ---- projection ------------------------------------------------------------
 hipError_t launch_project(const void *Y, int dt, int64_t n, int m, int64_t ld, const float *mean,

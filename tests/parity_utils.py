@@ -15,6 +15,8 @@ from __future__ import annotations
 import numpy as np
 
 GAP = 1e-3
+# sin(theta_max) of the leading-k subspace, wherever the gap rule applies.
+SUBSPACE_TOL = 1e-4
 
 
 def eig_err(lam_hat, lam):

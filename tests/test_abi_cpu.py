@@ -84,9 +84,11 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert so.pca_center(fake, lib.PCA_IN_F32_BSQ, 100, 8, 100, fake, fake, 8, fake, 1 << 20, null) == ARG
     assert so.pca_covariance(fake, 4, 100, 8, 100, 0, null, 0, fake, fake, 1 << 20, null) == ARG
     # Jacobi: negative tolerance, too many bands, misaligned workspace, an
-    # unknown flag bit.
+    # unknown flag bit, both forms at once.
     assert so.pca_jacobi_eigh(fake, 8, -1.0, 10, 1, fake, fake, null, fake, 1 << 20, null) == ARG
-    assert so.pca_jacobi_eigh(fake, 8, 1e-6, 10, 4, fake, fake, null, fake, 1 << 20, null) == ARG
+    assert so.pca_jacobi_eigh(fake, 8, 1e-6, 10, 16, fake, fake, null, fake, 1 << 20, null) == ARG
+    assert so.pca_jacobi_eigh(fake, 8, 1e-6, 10, lib.PCA_JACOBI_ONE_CU | lib.PCA_JACOBI_BLOCK, fake, fake, null,
+                              fake, 1 << 20, null) == ARG
     assert so.pca_jacobi_eigh(fake, 8, 1e-6, 10, -1, fake, fake, null, fake, 1 << 20, null) == ARG
     assert so.pca_jacobi_eigh(fake, 300, 1e-6, 10, 1, fake, fake, null, fake, 1 << 20, null) == ARG
     assert so.pca_jacobi_eigh(fake, 8, 1e-6, 10, 1, fake, fake, null, ctypes.c_void_p(4100), 1 << 20,

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import synth
-from parity_utils import eig_err, report
+from parity_utils import eig_err, report, SUBSPACE_TOL
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -78,6 +78,7 @@ def check_against_oracle(P, b, cubes, ks, label):
         assert r["eig"] <= EIG_TOL, (i, r)
         assert r["angle"] <= ANGLE_TOL, (i, r)
         assert r["proj"] <= PROJ_TOL, (i, r)
+        assert r.get("subspace", 0.0) <= SUBSPACE_TOL, (i, r)
         assert mu_err <= 1e-6
 
 

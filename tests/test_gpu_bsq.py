@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from parity_utils import report
+from parity_utils import report, SUBSPACE_TOL
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -137,6 +137,7 @@ def test_bsq_end_to_end(pca, dtype):
         say(f"bsq {dtype} {mode}: eig {rep['eig']:.2e} angle {rep['angle']:.2e} proj {rep['proj']:.2e}")
         assert pca.read_info(r.info)["converged"] == 1
         assert rep["eig"] <= EIG_TOL and rep["angle"] <= ANGLE_TOL and rep["proj"] <= PROJ_TOL
+        assert rep.get("subspace", 0.0) <= SUBSPACE_TOL, rep
         Qi = torch.empty(n, k, dtype=torch.float32, device="cuda")
         pca.pca_project(torch.from_numpy(Yh).cuda(), r.mean, r.V, k, Qi)
         Qb = host(r.Q)

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from parity_utils import eig_err, report
+from parity_utils import eig_err, report, SUBSPACE_TOL
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -128,6 +128,7 @@ def test_overlap_pipeline_oracle_and_graph(pca):
     r = report(outs[0], outs[1], outs[2], ref, k)
     say(f"c2 overlapped: {r}")
     assert r["eig"] <= 1e-5 and r["angle"] <= 1e-4 and r["proj"] <= 1e-4
+    assert r.get("subspace", 0.0) <= SUBSPACE_TOL, r
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())

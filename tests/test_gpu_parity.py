@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from parity_utils import eig_err, report, sign_rule_holds
+from parity_utils import eig_err, report, sign_rule_holds, SUBSPACE_TOL
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -154,6 +154,7 @@ def test_jacobi_planted(pca, m):
     assert eig_err(lam, ref_l) <= EIG_TOL
     r = report(lam, V, None, dict(lam=ref_l, V=ref_V, Q=None), m)
     assert r["angle"] <= ANGLE_TOL, r
+    assert r.get("subspace", 0.0) <= SUBSPACE_TOL, r
     assert sign_rule_holds(V, list(range(m)))
     assert np.abs(V.T @ V - np.eye(m)).max() <= 1e-5
 
@@ -206,6 +207,7 @@ def test_end_to_end(pca, name, mode):
     assert r["info"]["converged"] == 1
     assert r["eig"] <= EIG_TOL, r
     assert r["angle"] <= ANGLE_TOL, r
+    assert r.get("subspace", 0.0) <= SUBSPACE_TOL, r
     assert r["proj"] <= PROJ_TOL, r
     assert r["mean"] <= 1e-6, r
 
@@ -218,6 +220,7 @@ def test_end_to_end_224_band_cube(pca, mode):
     assert r["info"]["converged"] == 1
     assert r["eig"] <= EIG_TOL, r
     assert r["angle"] <= ANGLE_TOL, r
+    assert r.get("subspace", 0.0) <= SUBSPACE_TOL, r
     assert r["proj"] <= PROJ_TOL, r
 
 

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from parity_utils import report
+from parity_utils import report, SUBSPACE_TOL
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -58,6 +58,7 @@ def test_stream_matches_single_pipeline(pca, chain):
         rep = report(ref[i][1], ref[i][2], ref[i][3], oracle.pca(Y, k), k)
         say(f"stream cube {i}: eig {rep['eig']:.2e} angle {rep['angle']:.2e}")
         assert rep["eig"] <= 1e-5 and rep["angle"] <= 1e-4
+        assert rep.get("subspace", 0.0) <= SUBSPACE_TOL, rep
 
 
 def test_stream_overlapped_results(pca):

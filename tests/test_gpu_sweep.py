@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from parity_utils import report
+from parity_utils import report, SUBSPACE_TOL
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,3 +44,4 @@ def test_sweep_shape(pca, i, mode):
     assert info["converged"] == 1
     assert r["eig"] <= 1e-5
     assert r["angle"] <= 1e-4 and r["proj"] <= 1e-4
+    assert r.get("subspace", 0.0) <= SUBSPACE_TOL, r
