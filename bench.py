@@ -44,8 +44,10 @@ if ROOT not in sys.path:
 METRIC = "end-to-end PCA Mpixel·band/s; split-BF16 vs FP32 at ≤1e-5 eigval error"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, datasheet
 MFMA_F32_PEAK_TFS = 157.3      # dense FP32 matrix
+FP32_VECTOR_PEAK_TFS = 157.3   # FP32 vector (packed FMA counted), 256 CUs at 2.4 GHz
 MFMA_BF16_PEAK_TFS = 2500.0    # dense BF16 matrix
 EIG_TOL = 1e-5
+JACOBI_BLOCK_MIN_BANDS = 96    # the library's default form: block-cyclic from this band count
 
 
 def log(*a):
@@ -120,12 +122,26 @@ def time_stream(P, torch, n, m, k, mode, cubes, count, warmup, depth, chain=True
     return ms, wall, ok, ps, [round(r[0], 4) for r in runs]
 
 
-def cpu_baseline(oracle, Y, k, budget_s=12.0, max_runs=5):
-    """The FP64 oracle on the same cube, repeated until ~budget_s of work."""
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_info
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(oracle, Y, k, budget_s=12.0, max_runs=3, one_thread_pixels=1 << 17):
+    """The FP64 oracle on the same cube, repeated until ~budget_s of work with
+    the host's BLAS threads, then once with one thread on a leading sample of
+    one_thread_pixels pixels (the oracle's Jacobi is single-threaded C)."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     times = []
     t_all = time.perf_counter()
@@ -135,9 +151,19 @@ def cpu_baseline(oracle, Y, k, budget_s=12.0, max_runs=5):
         times.append(time.perf_counter() - t0)
     med = statistics.median(times)
     n, m = Y.shape
-    return dict(value=round(n * m / med / 1e6, 3), unit="Mpixel·band/s", cores=int(threads), kind="oracle",
-                sample=f"full cube {n} px x {m} bands, k={k}, float64 mean/covariance/row-cyclic Jacobi/"
-                       f"projection; median of {len(times)} runs ({med:.2f} s each)")
+    out = dict(value=round(n * m / med / 1e6, 3), unit="Mpixel·band/s", cores=int(threads), kind="oracle",
+               sample=f"full cube {n} px x {m} bands, k={k}, float64 mean/covariance/row-cyclic Jacobi/"
+                      f"projection; median of {len(times)} runs ({med:.2f} s each)",
+               cpu_model=cpu_model())
+    if threadpool_limits is not None:
+        Ys = Y[:one_thread_pixels]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle.pca(Ys, k)
+            t1 = time.perf_counter() - t0
+        out["one_thread"] = dict(value=round(Ys.shape[0] * m / t1 / 1e6, 3), unit="Mpixel·band/s", cores=1,
+                                 sample=f"leading {Ys.shape[0]} px x {m} bands, one run ({t1:.2f} s)")
+    return out
 
 
 def copy_check(torch, nbytes=1 << 30, reps=5):
@@ -181,47 +207,73 @@ def measured_traffic(kernel):
     return None if rec is None else rec.get("bytes_per_launch")
 
 
-def bench_batch(P, synth, torch, args):
+def run_batch(P, synth, torch, steps, warmup, mode="f32", lanes=1, autotune=False, check=0):
     """The batched form: 64 cubes with square sides 64..512 and 64..256 bands,
     k = 5, through pca_batched calls (one per lane: sub-batches by band count
-    on their own HIP streams) captured in one HIP graph."""
+    on their own HIP streams) captured in one HIP graph. check > 0: the
+    eigenvalues of that many cubes (the widest and the narrowest alternately)
+    against the FP64 oracle."""
+    import numpy as np
     log("generating the 64-cube batch ...")
     cubes = synth.make_batch(64, 4000)
     Yd = [torch.from_numpy(Y).cuda() for Y in cubes]
-    del cubes
-    mode = args.modes.split(",")[0] if args.modes != "f32,bf16x3,bf16x4" else "bf16x3"
-    b = P.BatchedPCA(Yd, 5, mode, lanes=args.lanes)
+    b = P.BatchedPCA(Yd, 5, mode, lanes=lanes)
     tuning = None
-    if args.autotune:
-        from paper_2403_18321_amd import autotune
-        tuning, _ = autotune.tune(b)
+    if autotune:
+        from paper_2403_18321_amd import autotune as _at
+        tuning, _ = _at.tune(b)
     g = b.capture()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         g.replay()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         g.replay()
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = e0.elapsed_time(e1) / steps
     pb = b.pixel_bands()
     conv = sum(P.read_info(i)["converged"] for i in b.info)
-    out = dict(metric=METRIC, value=round(pb / (ms * 1e-3) / 1e6, 1), unit="Mpixel·band/s", n_gpus=1,
-               steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True,
-               scaling="weak", vs_baseline=None, dtype="bf16" if mode.startswith("bf16") else "f32",
-               data="synthetic",
-               config=dict(workload="64 cubes, square sides 64..512 px, 64..256 bands, k=5 (pca_batched per lane, "
-                                    "graph replay)", pixel_bands=pb, cov_mode=mode, tuning=tuning,
-                           lanes=[len(g) for g in b.groups], converged=f"{conv}/{len(b.info)}"))
+    rec = dict(value=round(pb / (ms * 1e-3) / 1e6, 1), unit="Mpixel·band/s", ms_per_step=round(ms, 4),
+               dtype="bf16" if mode.startswith("bf16") else "f32", cov_mode=mode, pixel_bands=pb, tuning=tuning,
+               lanes=[len(gg) for gg in b.groups], converged=f"{conv}/{len(b.info)}",
+               workload="64 cubes, square sides 64..512 px, 64..256 bands, k=5 (pca_batched per lane, graph replay)")
+    if check > 0:
+        import oracle
+        order = sorted(range(len(cubes)), key=lambda i: cubes[i].shape[1] * cubes[i].shape[0])
+        pick = []
+        while len(pick) < min(check, len(order)):
+            pick.append(order.pop(-1 if len(pick) % 2 == 0 else 0))
+        errs = []
+        for i in pick:
+            lam_ref = oracle.pca(cubes[i], 5)["lam"]
+            lam = b.eigvals[i].cpu().numpy().astype(np.float64)
+            errs.append(float(np.max(np.abs(lam - lam_ref)) / abs(lam_ref[0])))
+        rec["eig_err_max"] = max(errs)
+        rec["checked_cubes"] = pick
+    del Yd, cubes, b, g
+    return rec
+
+
+def bench_batch(P, synth, torch, args):
+    mode = args.modes.split(",")[0] if args.modes != "f32,bf16x3,bf16x4" else "f32"
+    rec = run_batch(P, synth, torch, args.steps, args.warmup, mode, args.lanes, args.autotune,
+                    0 if args.no_accuracy else 8)
+    out = dict(metric=METRIC, value=rec["value"], unit="Mpixel·band/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=rec["ms_per_step"], higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype=rec["dtype"], data="synthetic",
+               config=dict(workload=rec["workload"], pixel_bands=rec["pixel_bands"], cov_mode=mode,
+                           tuning=rec["tuning"], lanes=rec["lanes"], converged=rec["converged"]))
+    if "eig_err_max" in rec:
+        out["eig_err_max"] = rec["eig_err_max"]
     print(json.dumps(out), flush=True)
     return 0
 
 
-def bench_grad(P, synth, torch, args):
+def run_grad(P, synth, torch, steps, warmup, check=True):
     """The differentiation form: the planted 256x256-pixel, 128-band cube,
     k = 8, float32; one step = the forward pipeline plus pca_backward for the
     loss <W, Q> (W a fixed random [pixels, k] array), whose gradient goes
@@ -243,7 +295,7 @@ def bench_grad(P, synth, torch, args):
         pipe.forward(Yd)
         P.pca_backward(Yd, pipe.mean, pipe.eigvals, pipe.V, k, dY, Wd, None, None, ws)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -252,12 +304,12 @@ def bench_grad(P, synth, torch, args):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    reps = max(3, min(args.steps, 10))
+    ms = e0.elapsed_time(e1) / steps
+    reps = max(3, min(steps, 10))
     for _ in range(reps):
         ev[0].record(stream)
         pipe.forward(Yd)
@@ -267,17 +319,26 @@ def bench_grad(P, synth, torch, args):
         torch.cuda.synchronize()
         t_fwd += ev[0].elapsed_time(ev[1]) / reps
         t_bwd += ev[1].elapsed_time(ev[2]) / reps
-    out = dict(metric="forward + adjoint PCA Mpixel·band/s", value=round(n * m / (ms * 1e-3) / 1e6, 1),
-               unit="Mpixel·band/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4),
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload="planted cube 256x256 px x 128 bands, k=8, loss <W, Q> (forward + pca_backward)",
-                           n_pixels=n, n_bands=m, k=k),
-               stages_ms=dict(forward=round(t_fwd, 4), backward=round(t_bwd, 4)))
-    if not args.no_accuracy:
+    rec = dict(value=round(n * m / (ms * 1e-3) / 1e6, 1), unit="Mpixel·band/s", ms_per_step=round(ms, 4),
+               dtype="f32", workload="planted cube 256x256 px x 128 bands, k=8, loss <W, Q> (forward + pca_backward)",
+               n_pixels=n, n_bands=m, k=k, stages_ms=dict(forward=round(t_fwd, 4), backward=round(t_bwd, 4)))
+    if check:
         import oracle
         ref = oracle.backward(Yh.astype(np.float64), k, dQ=W.astype(np.float64))
         g = dY.cpu().numpy().astype(np.float64)
-        out["grad_rel_err"] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+        rec["grad_rel_err"] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    return rec
+
+
+def bench_grad(P, synth, torch, args):
+    rec = run_grad(P, synth, torch, args.steps, args.warmup, not args.no_accuracy)
+    out = dict(metric="forward + adjoint PCA Mpixel·band/s", value=rec["value"], unit="Mpixel·band/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=rec["ms_per_step"], higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=rec["workload"], n_pixels=rec["n_pixels"], n_bands=rec["n_bands"], k=rec["k"]),
+               stages_ms=rec["stages_ms"])
+    if "grad_rel_err" in rec:
+        out["grad_rel_err"] = rec["grad_rel_err"]
     print(json.dumps(out), flush=True)
     return 0
 
@@ -329,6 +390,7 @@ def main(argv=None):
     ap.add_argument("--modes", default="f32,bf16x3,bf16x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="cube224: skip the batch64 and grad sub-records")
     ap.add_argument("--workload", choices=("cube224", "batch64", "grad", "sweep"), default="cube224",
                     help="cube224: the 224-band 1024x1024 cube (the reported line); batch64: the 64-cube batch; "
                          "grad: the differentiation form (forward + adjoint); sweep: the paper's sweep shapes")
@@ -390,10 +452,13 @@ def main(argv=None):
         rec = dict(ms_per_step=round(ms, 4), value=round(n * m / (ms * 1e-3) / 1e6, 1),
                    wall_s=round(wall, 3), stages_ms={kk: round(v, 4) for kk, v in stages.items()},
                    sweeps=info["sweeps"], steps_jacobi=info["steps"], off_rel=info["off_rel"],
-                   converged=info["converged"])
+                   converged=info["converged"], jacobi_form="block" if m >= JACOBI_BLOCK_MIN_BANDS else "one_cu")
         if ref is not None:
             r = report(pipe.eigvals.cpu().numpy(), pipe.V.cpu().numpy(), pipe.Q.cpu().numpy(), ref, k)
-            rec.update(eig_err=r["eig"], angle_err=r["angle"], proj_err=r["proj"])
+            Cg = pipe.C.cpu().numpy().astype(np.float64)
+            rec.update(eig_err=r["eig"], angle_err=r["angle"], proj_err=r["proj"], subspace_sin=r.get("subspace"),
+                       cov_err_fro=float(np.linalg.norm(Cg - ref["C"]) / np.linalg.norm(ref["C"])),
+                       cov_err_max=float(np.abs(Cg - ref["C"]).max() / np.abs(ref["C"]).max()))
         modes[mode] = rec
         log(mode, json.dumps(rec))
 
@@ -401,34 +466,38 @@ def main(argv=None):
     best = min(ok or list(modes), key=lambda mm: modes[mm]["ms_per_step"])
     br = modes[best]
 
-    # Roofline of the dominant kernel of the best form.
+    # Rooflines. End to end: the algorithmic bytes of the method (the cube
+    # read twice, by the covariance with fused centring and by the
+    # projection, plus Q' written) at the HBM peak, against the step time.
+    b_in = 4
+    e2e_bytes = 2 * n * m * b_in + n * k * 4
+    t_roof = e2e_bytes / (HBM_PEAK_GBS * 1e9) * 1e3
+    e2e = dict(bytes=e2e_bytes, t_roof_ms=round(t_roof, 4), ms_per_step=br["ms_per_step"],
+               frac=round(t_roof / br["ms_per_step"], 4))
     stages = br["stages_ms"]
-    dom = max(stages, key=stages.get)
-    t = stages[dom] * 1e-3
-    if dom == "covariance":
-        if best == "f32":
-            flops = n * m * (m + 1)
-            achieved = flops / t / 1e12
-            roof = dict(bound="mfma", achieved=round(achieved, 2), peak=MFMA_F32_PEAK_TFS, unit="TFLOP/s")
-        else:
-            bytes_ = n * m * 4
-            achieved = bytes_ / t / 1e9
-            roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s")
-    elif dom == "project":
-        bytes_ = n * m * 4 + n * k * 4
-        achieved = bytes_ / t / 1e9
-        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s")
+    me = m + (m & 1)
+    kern = {}
+    t_cov = stages["covariance"] * 1e-3
+    if best == "f32":
+        a = n * m * (m + 1) / t_cov / 1e12
+        kern["covariance"] = dict(bound="mfma", achieved=round(a, 2), peak=MFMA_F32_PEAK_TFS, unit="TFLOP/s",
+                                  frac=round(a / MFMA_F32_PEAK_TFS, 4))
     else:
-        # One workgroup on one CU: the bound is that CU's float32 FMA rate
-        # without packed instructions, 64 lanes x 2 flop x 2.4 GHz = 307.2
-        # GFLOP/s. Algorithmic work: 24 flops per off-diagonal 2x2 block
-        # (both sides of the rotation), (M/2)(M/2 - 1)/2 blocks per step.
-        me = m + (m & 1)
-        pairs = me // 2
-        flops = br["steps_jacobi"] * 24 * pairs * (pairs - 1) // 2
-        achieved = flops / t / 1e9
-        roof = dict(bound="alu", achieved=round(achieved, 1), peak=307.2, unit="GFLOP/s")
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+        a = n * m * b_in / t_cov / 1e9
+        kern["covariance"] = dict(bound="hbm", achieved=round(a, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                                  frac=round(a / HBM_PEAK_GBS, 4))
+    a = (n * m * b_in + n * k * 4) / (stages["project"] * 1e-3) / 1e9
+    kern["project"] = dict(bound="hbm", achieved=round(a, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                           frac=round(a / HBM_PEAK_GBS, 4))
+    # Jacobi: about 6 M^3 flops per sweep (two-sided rotation of every index
+    # pair once), against the chip's float32 vector peak.
+    jac_flops = 6.0 * me ** 3 * max(br["sweeps"], 1)
+    a = jac_flops / (stages["jacobi_eigh"] * 1e-3) / 1e12
+    kern["jacobi_eigh"] = dict(bound="alu", achieved=round(a, 4), peak=FP32_VECTOR_PEAK_TFS, unit="TFLOP/s",
+                               frac=round(a / FP32_VECTOR_PEAK_TFS, 5), flops=jac_flops, sweeps=br["sweeps"],
+                               form=br["jacobi_form"])
+    dom = max(stages, key=stages.get)
+    roof = dict(kern[dom])
     roof["kernel"] = dom
     roof["traffic"] = measured_traffic(dom + ":" + best)
 
@@ -437,7 +506,7 @@ def main(argv=None):
                vs_baseline=None, dtype={"f32": "f32", "bf16x3": "bf16", "bf16x4": "bf16"}[best], data="synthetic",
                config=dict(workload="224-band radiance cube, 1024x1024 px (uint16 counts -> float32), k=10",
                            n_pixels=n, n_bands=m, k=k, cov_mode=best),
-               roofline=roof, modes=modes)
+               roofline=roof, e2e_roofline=e2e, kernels=kern, modes=modes)
     # Other ingest forms of the same cube, best covariance form: the raw
     # uint16 counts read directly (half the bytes of the float32 cube), and
     # the band-sequential float32 layout of the paper's GPU design.
@@ -477,6 +546,17 @@ def main(argv=None):
         out["stream"] = rec
         log("stream", json.dumps(rec))
         del cubes, ps
+    if not args.no_secondary:
+        # The other workloads, each timed here under the same clock: the
+        # 64-cube batch (float32, eigenvalues of 4 cubes against the oracle)
+        # and the differentiation form (gradient against the oracle's).
+        del Yd
+        torch.cuda.empty_cache()
+        out["batch64"] = run_batch(P, synth, torch, max(3, args.steps // 4), 2, "f32", check=0 if args.no_accuracy else 4)
+        log("batch64", json.dumps(out["batch64"]))
+        torch.cuda.empty_cache()
+        out["grad"] = run_grad(P, synth, torch, args.steps, args.warmup, not args.no_accuracy)
+        log("grad", json.dumps(out["grad"]))
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(oracle, Yu, k)

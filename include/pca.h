@@ -179,14 +179,14 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
  * together (the parallel-rotation property stated at the end of Section 2):
  *   - one workgroup holds the matrix in LDS and applies n_bands/2 rotations
  *     per parallel step in round-robin order, n_bands - 1 steps per sweep
- *     (PCA_JACOBI_ONE_CU; the default below 224 bands);
+ *     (PCA_JACOBI_ONE_CU; the default below 96 bands);
  *   - block-cyclic: the indices are grouped in blocks of 16, a round-robin
  *     over the blocks pairs them, and one workgroup per pair of block pairs
  *     rotates its pair's index pairs and applies the product of those
  *     rotations to its tiles of A and of the eigenvector matrix (equations
  *     (8) and (10) with the rotations of a step grouped); the workgroups
  *     exchange tiles through memory once per block step (PCA_JACOBI_BLOCK;
- *     the default from 224 bands). Every index pair is still rotated once per
+ *     the default from 96 bands). Every index pair is still rotated once per
  *     sweep; only the order differs. It spreads one call over up to 32 CUs
  *     and needs them all resident at once, so it pays when the call has the
  *     GPU to itself; a workgroup that waits about half a second for the

@@ -40,7 +40,7 @@ class PCAPipeline:
         Jacobi, form the eigenvectors while the sweeps run, on other CUs of
         the same launch (for a cube that has the GPU to itself; a stream of
         cubes leaves those CUs to the other cubes' passes). jacobi: "auto"
-        (block-cyclic on many CUs from 224 bands, one workgroup below),
+        (block-cyclic on many CUs from 96 bands, one workgroup below),
         "block" or "one_cu"."""
         self.n, self.m, self.k = int(n_pixels), int(n_bands), int(k)
         self.layout = layout

@@ -11,7 +11,10 @@
 //   - cross steps c = 0..15: index I_k with J_{(k + c) mod 16}, so that over
 //     one outer step every pair (i in I, j in J) is rotated once;
 //   - in the first outer step of every sweep, 15 intra steps before the
-//     cross steps: a round-robin within I and within J.
+//     cross steps, in four levels h = 8, 4, 2, 1: at level h each block is
+//     cut into groups of 2h indices, and the first h of a group meet the
+//     last h in h steps (member o with member (o + c) mod h), so that every
+//     pair inside I and inside J is rotated once.
 // Over one sweep every index pair is rotated exactly once, as in the
 // row-by-row cyclic order of Section 2 (only the order differs; the paper
 // leaves the order open and its two designs use two other orders).
@@ -26,34 +29,46 @@
 //   formed by whoever needs it at step t + 1).
 // Workgroup (x, g) of the P x Q grid owns, at step t, the rows of block pair
 // x of step t and the columns of the block pairs j = g, g + Q, ... of step
-// t - 1:
-//   1. D = A_t[pair x, pair x] from two tiles of H_{t-1} and two U's;
-//   2. the inner rotations on D (a float32 copy in LDS, one barrier per inner
-//      step) give U_{t,x}, accumulated in float64; every workgroup of row x
-//      forms the same U_{t,x};
-//   3. for each of its column pairs j: R = A_t[pair x, pair j] =
-//      H_{t-1}[..] U_{t-1,j}, H_t[pair x, pair j] = U_{t,x}^T R (float64
-//      MFMA products of 32 x 32 tiles) and V_t[pair x rows, pair j cols] =
-//      V_{t-1}[..] U_{t-1,j} (float32 MFMA);
-//   4. R also gives this tile's part of off(A_t)^2, ||A_t||_F^2 and the
-//      diagonal of A_t;
-//   5. a grid barrier (per-workgroup step flags).
-// The stop rule (off(A)/||C||_F <= tol, a sweep without any rotation, or
-// max_sweeps) is evaluated at the start of every sweep from the partial sums
-// of all workgroups, added in workgroup order, so every workgroup reaches the
-// same decision. At the stop, A_t's diagonal is the eigenvalues and V_t the
-// eigenvectors (unsorted; sort_sign_kernel follows).
+// t - 1. Its eight waves split a step as follows:
+//   A. all: load the step's tiles (one round trip for all of them);
+//   B. waves 0-3: D = A_t[pair x, pair x] from two tiles of H_{t-1} and two
+//      U's (float64 MFMA); waves 4-7: R = A_t[pair x, first column pair] =
+//      H_{t-1}[..] U_{t-1,j};
+//   C. wave 0: the inner rotations on D, held in registers (below), which
+//      publish every step's rotations in LDS; waves 1-2: U_{t,x} from those
+//      rotations in float64, one step behind; waves 3-7: the second column
+//      pair's R, V_t[pair x rows, pair j cols] = V_{t-1}[..] U_{t-1,j}
+//      (float32 MFMA), and the tiles' shares of off(A_t)^2, ||A_t||_F^2;
+//   D. all: H_t[pair x, pair j] = U_{t,x}^T R (float64 MFMA), stored with
+//      U_{t,x} and the partial sums; then a grid barrier.
+// Every workgroup of row x forms the same U_{t,x}. The stop rule (off(A)/
+// ||C||_F <= tol, a sweep without any rotation, or max_sweeps) is evaluated
+// at the start of every sweep from the partial sums of all workgroups, added
+// in workgroup order, so every workgroup reaches the same decision. At the
+// stop, A_t's diagonal is the eigenvalues and V_t the eigenvectors (unsorted;
+// sort_sign_kernel follows).
 //
-// Inner rotations. The thread that produces the next pivot computes its
-// rotation, and the diagonal after every step is carried in the rotation
-// records, so one barrier per inner step suffices. They run in float32 (the
-// tangent in float64 with PCA_JACOBI_FP64_ANGLES); U accumulates them in
-// float64 with (cos, sin) normalised in float64. The inner sub-matrix only
-// serves to find U: A itself is carried by the float64 tile products with U
-// orthogonal to float64 rounding, so the precision of the inner steps sets
-// how fast the iteration converges, not the accuracy of the result (a
-// rotation that leaves a small residue at its pivot is itself orthogonal;
-// the residue is rotated again later).
+// Inner rotations in registers. Wave 0 holds D in a relabelled order: the
+// 16 rotation pairs of a phase (a level of the intra steps, or the cross
+// steps) are (position k, position 16 + sigma_c(k)), k = 0..15, where sigma_c
+// turns k by c inside its group of h positions. Lane 16 kg + l holds, for
+// k = 4 kg + r (slots r = 0..3), the 2 x 2 block of rows (k, 16 + sigma_c(k))
+// and columns (l, 16 + sigma_c(l)), so a step is four two-sided 2 x 2
+// rotations per lane with no exchange; afterwards the second-member rows
+// and columns move one group position on (in-lane slot renaming and lane
+// permutes) to form the next step's blocks. The next step's pivot of pair k
+// lies in the block (k, next(k)) of this step, so the lane holding it forms
+// that rotation right after its own update (the diagonal after the step
+// comes in closed form with the rotation records), and one LDS round trip
+// per step publishes the 16 rotations to every lane and to waves 1-2. The
+// rotations run in float32 (the tangent in float64 with
+// PCA_JACOBI_FP64_ANGLES); U accumulates them in float64 with (cos, sin)
+// normalised in float64. The inner sub-matrix only serves to find U: A itself
+// is carried by the float64 tile products with U orthogonal to float64
+// rounding, so the precision of the inner steps sets how fast the iteration
+// converges, not the accuracy of the result (a rotation that leaves a small
+// residue at its pivot is itself orthogonal; the residue is rotated again
+// later).
 //
 // Placement and synchronisation. Launch 8 G workgroups of which every 8th
 // (one residue class, rotated from call to call) takes part, so that, with
@@ -65,9 +80,10 @@
 // their XCD ids over device-scope memory; if they are not all on one XCD the
 // call uses device-scope release/acquire fences for every step instead.
 // Every wait is bounded in time: a workgroup that waits about half a second
-// for the others gives up, and the call reports nonfinite output (NaN), so
-// the launch always ends. Step flags are cleared by bj_clear_kernel before
-// every launch, so a call does not depend on what the workspace held.
+// for the others gives up (and waves 1-2 give up on wave 0 likewise), and the
+// call reports nonfinite output (NaN), so the launch always ends. Step flags
+// are cleared by bj_clear_kernel before every launch, so a call does not
+// depend on what the workspace held.
 #include <math.h>
 
 #include "common.hpp"
@@ -86,8 +102,6 @@ constexpr int kLdd = 34;       // LDS pitch of a float64 32 x 32 tile
 constexpr int kTile = 32 * kLd;
 constexpr int kTiled = 32 * kLdd;
 constexpr int kNS = 31;        // inner steps of the first outer step of a sweep
-constexpr int kC0 = 15;        // index of the first cross step
-constexpr int kUpper = 120;    // 2x2 blocks (k < l) of 16 pairs
 constexpr int kCg = kBjMaxColPairs;   // column pairs per workgroup, at most
 constexpr long long kWaitTicks = 50000000;   // 0.5 s of the 100 MHz real-time counter
 constexpr unsigned kRsrcWord3 = 0x00020000u;  // raw buffer resource, gfx9 family
@@ -101,54 +115,47 @@ struct BjPart {
 static_assert(sizeof(BjPart) == 32, "partial-sum record size is part of the workspace layout");
 
 struct Smem {
-    double T1[kTiled], T2[kTiled], U1[kTiled], U2[kTiled];
-    double Tj[kCg][kTiled], Uj[kCg][kTiled], R[kCg][kTiled];
-    double Ui[kTiled];
-    float Ujf[kCg][kTile], Vb[kCg][kTile];
-    float D[kTile];
-    unsigned char sp[kC0 + 1][16], sq[kC0 + 1][16], pid[kC0 + 1][32];   // intra steps and cross step 0
-    unsigned char prodA[kC0][kUpper], prodB[kC0][kUpper];                // productions of the intra steps
-    float2 rcf[2][16];      // (cos, sin) of each pair's rotation
-    float2 rdg[2][16];      // the pair's diagonal (a_pp, a_qq) after the step
-    float rpv[2][16];       // pivot entry after the step
-    int rap[2][16];         // 1 when the rotation was applied
-    double red[2][8];
+    double T1[kTiled], T2[kTiled], U1[kTiled], U2[kTiled];   // operands of D
+    double Tj[kCg][kTiled], Uj[kCg][kTiled];                 // operands of R
+    double R[kCg][kTiled];                                   // A_t[pair x, column pair]
+    double Ui[kTiled];                                       // U_{t,x}
+    float Ujf[kCg][kTile], Vb[kCg][kTile], Vo[kCg][kTile];   // V_{t-1} tiles, U_{t-1,j}, V_t tiles
+    float D[kTile];                                          // A_t[pair x, pair x] (float32)
+    float4 rec[kNS][16];   // rotation records of the inner steps: (cos, sin, a_pp, a_qq after)
+    double red[2][2 * kCg * 4];   // per-tile off and total sums of squares of R
+    int pub;               // inner steps whose records are published (wave 0 to waves 1-2)
     int st_bad, st_cnt, st_fail;
+#ifdef BJ_PROFILE
+    long long prof_w[8];
+#endif
 };
 
-// Rotation of the pivot block [[app, apq], [apq, aqq]] of the float32
-// sub-matrix (equations (2)-(5) with (7), the cancellation-free form of the
-// tangent), written into record slot (par, k): cos, sin, the diagonal after
-// the step a_pp - t a_pq, a_qq + t a_pq, the pivot after the step (0). fp64
-// evaluates the tangent in float64. Skipped (cos 1, sin 0) at the float32
-// rounding floor of the block.
-__device__ inline void make_rec(Smem &L, int par, int k, float app, float aqq, float apq, float floor_abs, int fp64)
+// Rotation of the pivot block [[app, apq], [apq, aqq]] (equations (2)-(5)
+// with (7), the cancellation-free form of the tangent) as a record (cos,
+// sin, a_pp - t a_pq, a_qq + t a_pq): row p becomes cos p - sin q, row q
+// sin p + cos q, and the pivot vanishes. FP64 evaluates the tangent in
+// float64. Skipped (cos 1, sin 0, diagonal unchanged) at the float32
+// rounding floor of the block. No branches: every lane of the wave computes
+// it and the caller keeps the records it needs.
+template <bool FP64>
+__device__ inline float4 make_rec(float app, float aqq, float apq, float floor_abs, int &applied)
 {
     const float ad = fabsf(apq);
-    float c = 1.f, s = 0.f, dp = app, dq = aqq, pv = apq;
-    int applied = 0;
-    if (ad > floor_abs && ad * ad > 3.5527137e-15f * fabsf(app * aqq)) {   // |a_pq| > 2^-24 sqrt(|a_pp a_qq|)
-        float tf;
-        if (fp64) {
-            const double d = (double)aqq - (double)app, a = (double)apq;
-            const double r = sqrt(fma(d, d, 4.0 * a * a));
-            tf = (float)((d >= 0.0 ? 2.0 * a : -2.0 * a) / (fabs(d) + r));
-        } else {
-            const float df = aqq - app;
-            const float rf = __builtin_amdgcn_sqrtf(fmaf(df, df, 4.f * apq * apq));
-            tf = (df >= 0.f ? 2.f * apq : -2.f * apq) * __builtin_amdgcn_rcpf(fabsf(df) + rf);
-        }
-        c = __builtin_amdgcn_rsqf(fmaf(tf, tf, 1.f));
-        s = tf * c;
-        dp = fmaf(-tf, apq, app);
-        dq = fmaf(tf, apq, aqq);
-        pv = 0.f;
-        applied = 1;
+    const bool on = ad > floor_abs && ad * ad > 3.5527137e-15f * fabsf(app * aqq);   // |a_pq| > 2^-24 sqrt(|a_pp a_qq|)
+    float tf;
+    if constexpr (FP64) {
+        const double d = (double)aqq - (double)app, a = (double)apq;
+        const double r = sqrt(fma(d, d, 4.0 * a * a));
+        tf = (float)((d >= 0.0 ? 2.0 * a : -2.0 * a) / (fabs(d) + r));
+    } else {
+        const float df = aqq - app;
+        const float rf = __builtin_amdgcn_sqrtf(fmaf(df, df, 4.f * apq * apq));
+        tf = (df >= 0.f ? 2.f * apq : -2.f * apq) * __builtin_amdgcn_rcpf(fabsf(df) + rf);
     }
-    L.rcf[par][k] = make_float2(c, s);
-    L.rdg[par][k] = make_float2(dp, dq);
-    L.rpv[par][k] = pv;
-    L.rap[par][k] = applied;
+    tf = on ? tf : 0.f;
+    const float c = __builtin_amdgcn_rsqf(fmaf(tf, tf, 1.f));
+    applied = on ? 1 : 0;
+    return make_float4(on ? c : 1.f, tf * c, fmaf(-tf, apq, app), fmaf(tf, apq, aqq));
 }
 
 // (cos, sin) of a record, normalised in float64 (one Newton step of
@@ -173,7 +180,6 @@ __device__ inline void rr_where(int n, int u, int a, int &k, int &side)
     else { k = n - 1 - i; side = 1; }
 }
 
-__device__ inline int sym(int i, int j) { return i < j ? i * kLd + j : j * kLd + i; }
 
 // 16 x 16 tile of op(A) B with K = 32 from LDS: A element (i, k) at
 // A[i * lda + k] (or A[k * lda + i] when transposed), B element (k, j) at
@@ -376,6 +382,340 @@ struct BjArgs {
     pca_info *info;
 };
 
+// ---- inner rotations (wave 0) and U (waves 1-2) ----------------------------
+
+// Position p (0..31) of phase H -> local index (0..31) of the block pair
+// (block I = 0..15, block J = 16..31). The cross phase (H = 16) is the
+// identity; intra level H takes, in each block, the first H indices of every
+// group of 2H to positions 0..7 (block I) or 8..15 (block J) and their
+// partners H further on to positions 16..31.
+template <int H>
+__device__ inline int ph_local(int p)
+{
+    if constexpr (H == 16) {
+        return p;
+    } else {
+        const int k = p & 15, kk = k & 7;
+        return ((k >> 3) << 4) + (kk / H) * (2 * H) + (kk % H) + (p >> 4) * H;
+    }
+}
+// Position k turned by c inside its group of H positions, and its successor.
+template <int H>
+__device__ inline int ph_sigma(int c, int k) { return (k & ~(H - 1)) | ((k + c) & (H - 1)); }
+template <int H>
+__device__ inline int ph_next(int k) { return ph_sigma<H>(1, k); }
+
+// Value v of lane src (any lane of the wave).
+__device__ inline float lane_take(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ inline double lane_take(double v, int src)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(b >> 32));
+    return __longlong_as_double(((long long)(unsigned)hi << 32) | (long long)(unsigned)lo);
+}
+
+// The value of lane 16 kg + next(l) of the same 16-lane row (next turns l
+// inside its group of H): DPP row rotations and quad permutations, which
+// move data between lanes without the LDS unit.
+template <int CTRL>
+__device__ inline float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int H>
+__device__ inline float col_next(float v, int l)
+{
+    if constexpr (H == 16) {
+        return dpp<0x12F>(v);                          // row_ror:15: lane i <- lane (i + 1) mod 16
+    } else if constexpr (H == 8) {
+        const float a = dpp<0x12F>(v), b = dpp<0x127>(v);   // row_ror:7: lane i <- lane (i - 7) mod 16
+        return (l & 7) == 7 ? b : a;
+    } else if constexpr (H == 4) {
+        return dpp<0x39>(v);                           // quad_perm [1, 2, 3, 0]
+    } else if constexpr (H == 2) {
+        return dpp<0xB1>(v);                           // quad_perm [1, 0, 3, 2]
+    } else {
+        return v;
+    }
+}
+template <int H>
+__device__ inline double col_next(double v, int l)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const float lo = col_next<H>(__int_as_float((int)(unsigned)b), l);
+    const float hi = col_next<H>(__int_as_float((int)(unsigned)(b >> 32)), l);
+    return __longlong_as_double(((long long)(unsigned)__float_as_int(hi) << 32) |
+                                (long long)(unsigned)__float_as_int(lo));
+}
+
+// Wave 0 tells waves 1-2 that the records of inner steps below n are in LDS. The
+// records were written earlier by this wave, and LDS carries out one wave's
+// accesses in order; the empty asm keeps the compiler from moving them.
+__device__ inline void publish(Smem &L, int n)
+{
+    asm volatile("" ::: "memory");
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(&L.pub, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    asm volatile("" ::: "memory");
+}
+// Waves 1-2 wait for the records of inner step s (bounded: false if wave 0
+// never publishes them).
+__device__ inline bool wait_pub(Smem &L, int s)
+{
+    int spins = 0;
+    while (__hip_atomic_load(&L.pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= s) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1 << 22)) return false;
+    }
+    asm volatile("" ::: "memory");
+    return true;
+}
+
+// Wave 0: the H inner steps of one phase, from inner step s0 on. D is read
+// from LDS (local index space) at the start and written back at the end
+// (kWrite). Returns the number of rotations applied by this lane's records.
+// A step: the four 2 x 2 updates; the shifted values' lane permutes are
+// issued; the pivot's owner forms the next step's rotation while they are in
+// flight; the next step's records are read back while the loop turns.
+template <int H, bool kWrite, bool FP64>
+__device__ __attribute__((noinline)) int inner_phase(Smem &L, int s0, float floor_abs)
+{
+    const int lane = threadIdx.x & 63, kg = lane >> 4, l = lane & 15;
+    float aII[4], aIJ[4], aJI[4], aJJ[4];
+    {
+        const int c0 = ph_local<H>(l), c1 = ph_local<H>(16 + l);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int r0 = ph_local<H>(4 * kg + r), r1 = ph_local<H>(16 + 4 * kg + r);
+            aII[r] = L.D[r0 * kLd + c0];
+            aIJ[r] = L.D[r0 * kLd + c1];
+            aJI[r] = L.D[r1 * kLd + c0];
+            aJJ[r] = L.D[r1 * kLd + c1];
+        }
+    }
+    int napplied = 0;
+    {
+        const int k = lane & 15;
+        const int p = ph_local<H>(k), q = ph_local<H>(16 + k);
+        int ap;
+        const float4 rc = make_rec<FP64>(L.D[p * kLd + p], L.D[q * kLd + q], L.D[p * kLd + q], floor_abs, ap);
+        if (lane < 16) {
+            L.rec[s0][lane] = rc;
+            napplied += ap;
+        }
+    }
+    publish(L, s0 + 1);
+    // The slot whose block holds the next step's pivot of a pair (if any),
+    // and the lanes the next step's values come from.
+    int rp = -1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (ph_next<H>(4 * kg + r) == l) rp = r;
+    const int kg_row = H == 16 ? ((kg + 1) & 3) : (kg ^ 1);   // H = 8, 16: where slot 3's next row lives
+    float4 rk[4], rl;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rk[r] = L.rec[s0][4 * kg + r];
+    rl = L.rec[s0][l];
+    for (int c = 0; c < H; ++c) {
+        const int s = s0 + c;
+        // Slot 0 first: the values that leave this 16-lane row for the next
+        // step (H = 8, 16) are sent while slots 1-3 are updated.
+        float x1 = 0.f, x2 = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float ck = rk[r].x, sk = rk[r].y;
+            const float yII = ck * aII[r] - sk * aJI[r], yJI = sk * aII[r] + ck * aJI[r];
+            const float yIJ = ck * aIJ[r] - sk * aJJ[r], yJJ = sk * aIJ[r] + ck * aJJ[r];
+            aII[r] = rl.x * yII - rl.y * yIJ;
+            aIJ[r] = rl.y * yII + rl.x * yIJ;
+            aJI[r] = rl.x * yJI - rl.y * yJJ;
+            aJJ[r] = rl.y * yJI + rl.x * yJJ;
+            if (r == 0 && H >= 8 && c < H - 1) {
+                x1 = lane_take(aJI[0], 16 * kg_row + l);
+                x2 = lane_take(aJJ[0], 16 * kg_row + ph_next<H>(l));
+            }
+        }
+        if (c == H - 1) break;
+        // The next step's rotation of pair 4 kg + rp: its pivot is this
+        // block's (k, next(k)) entry, its diagonal the closed forms carried
+        // by the records of pairs k and l = next(k).
+        {
+            float z = 0.f, dp = 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r == rp) { z = aIJ[r]; dp = rk[r].z; }
+            int ap;
+            const float4 rc = make_rec<FP64>(dp, rl.w, z, floor_abs, ap);
+            if (rp >= 0) {
+                L.rec[s + 1][4 * kg + rp] = rc;
+                napplied += ap;
+            }
+        }
+        publish(L, s + 2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rk[r] = L.rec[s + 1][4 * kg + r];
+        rl = L.rec[s + 1][l];
+        // Second members move one group position on: rows next(k) (in this
+        // lane, or slot 3 from another 16-lane row), columns next(l).
+        float nJI[4], nJJ[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int kn = ph_next<H>(r) & 3;   // slot of next(4 kg + r) when it stays in this lane
+            aIJ[r] = col_next<H>(aIJ[r], l);
+            if (H >= 8 && r == 3) {
+                nJI[r] = x1;
+                nJJ[r] = x2;
+            } else {
+                nJI[r] = aJI[kn];
+                nJJ[r] = col_next<H>(aJJ[kn], l);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { aJI[r] = nJI[r]; aJJ[r] = nJJ[r]; }
+    }
+    if constexpr (kWrite) {
+        const int c0 = ph_local<H>(l), c1 = ph_local<H>(16 + ph_sigma<H>(H - 1, l));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = 4 * kg + r;
+            const int r0 = ph_local<H>(k), r1 = ph_local<H>(16 + ph_sigma<H>(H - 1, k));
+            L.D[r0 * kLd + c0] = aII[r];
+            L.D[r0 * kLd + c1] = aIJ[r];
+            L.D[r1 * kLd + c0] = aJI[r];
+            L.D[r1 * kLd + c1] = aJJ[r];
+        }
+    }
+    return napplied;
+}
+
+// All inner steps of outer step t (the intra levels first at a sweep start).
+template <bool FP64>
+__device__ int inner_all(Smem &L, bool first, float floor_abs)
+{
+    int napp = 0;
+    if (first) {
+        napp += inner_phase<8, true, FP64>(L, 0, floor_abs);
+        napp += inner_phase<4, true, FP64>(L, 8, floor_abs);
+        napp += inner_phase<2, true, FP64>(L, 12, floor_abs);
+        napp += inner_phase<1, true, FP64>(L, 14, floor_abs);
+        napp += inner_phase<16, false, FP64>(L, 15, floor_abs);
+    } else {
+        napp += inner_phase<16, false, FP64>(L, 0, floor_abs);
+    }
+    return napp;
+}
+
+// Waves 1 and 2: U <- U P for the H steps of one phase, one step behind
+// wave 0. Wave 1 + h (h = 0, 1) holds rows 16 h .. 16 h + 15: lane 16 rg + l
+// the columns at positions l and 16 + sigma_c(l) of rows 16 h + 4 rg ..
+// 16 h + 4 rg + 3. U starts as the identity (first) or from LDS, and ends
+// in LDS. False if wave 0's records never came.
+template <int H>
+__device__ __attribute__((noinline)) bool u_phase(Smem &L, int s0, bool first, int h)
+{
+    const int lane = threadIdx.x & 63, rg = lane >> 4, l = lane & 15;
+    double uI[4], uJ[4];
+    {
+        const int c0 = ph_local<H>(l), c1 = ph_local<H>(16 + l);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int rho = 16 * h + 4 * rg + q;
+            uI[q] = first ? (rho == c0 ? 1.0 : 0.0) : L.Ui[rho * kLdd + c0];
+            uJ[q] = first ? (rho == c1 ? 1.0 : 0.0) : L.Ui[rho * kLdd + c1];
+        }
+    }
+    for (int c = 0; c < H; ++c) {
+        if (!wait_pub(L, s0 + c)) return false;
+        const float4 rr = L.rec[s0 + c][l];
+        const double2 cs = rot64(make_float2(rr.x, rr.y));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double a = uI[q], b = uJ[q];
+            uI[q] = cs.x * a - cs.y * b;
+            uJ[q] = cs.y * a + cs.x * b;
+        }
+        if (c < H - 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) uJ[q] = col_next<H>(uJ[q], l);
+        }
+    }
+    const int c0 = ph_local<H>(l), c1 = ph_local<H>(16 + ph_sigma<H>(H - 1, l));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rho = 16 * h + 4 * rg + q;
+        L.Ui[rho * kLdd + c0] = uI[q];
+        L.Ui[rho * kLdd + c1] = uJ[q];
+    }
+    return true;
+}
+
+// ---- tile tasks of the other waves ------------------------------------------
+
+// Shares of off(A_t)^2 and ||A_t||_F^2 of one 16 x 16 tile of R (this
+// lane's four entries), into slot e.
+__device__ inline void tile_sums(Smem &L, const double (&v)[4], int I, int J, int K, int Lb, int ti, int tj, int e)
+{
+    const int lane = threadIdx.x & 63, orow = 4 * (lane >> 4), ocol = lane & 15;
+    const int gc = lab(K, Lb, 16 * tj + ocol);
+    double so = 0.0, st = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double q = v[r] * v[r];
+        st += q;
+        if (lab(I, J, 16 * ti + orow + r) != gc) so += q;
+    }
+    so = wave_sum(so);
+    st = wave_sum(st);
+    if (lane == 0) {
+        L.red[0][e] = so;
+        L.red[1][e] = st;
+    }
+}
+
+// Tile (ti, tj) of R[jj] = Tj[jj] Uj[jj] (t > 0; at t = 0 R[jj] holds C's
+// tile already).
+__device__ inline void r_tile(Smem &L, int jj, int ti, int tj)
+{
+    const int lane = threadIdx.x & 63, orow = 4 * (lane >> 4), ocol = lane & 15;
+    const f64x4 acc = tile16d(L.Tj[jj] + 16 * ti * kLdd, kLdd, false, L.Uj[jj] + 16 * tj, kLdd);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) L.R[jj][(16 * ti + orow + r) * kLdd + 16 * tj + ocol] = acc[r];
+}
+// The sums of tile (ti, tj) of R[jj] (read back by the lanes that wrote it,
+// or any lanes once a barrier has passed).
+__device__ inline void r_sums(Smem &L, int jj, int ti, int tj, int I, int J, int K, int Lb)
+{
+    const int lane = threadIdx.x & 63, orow = 4 * (lane >> 4), ocol = lane & 15;
+    double v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = L.R[jj][(16 * ti + orow + r) * kLdd + 16 * tj + ocol];
+    tile_sums(L, v, I, J, K, Lb, ti, tj, 4 * jj + 2 * ti + tj);
+}
+
+// Tile (ti, tj) of V_t[pair x rows, column pair jj] = V_{t-1} U_{t-1,j}
+// (the identity's tile at t = 0): to global V and to Vo.
+__device__ inline void v_task(Smem &L, float *V, int Mp, int jj, int ti, int tj, bool first, int I, int J, int K,
+                              int Lb)
+{
+    const int lane = threadIdx.x & 63, orow = 4 * (lane >> 4), ocol = lane & 15;
+    const int gc = lab(K, Lb, 16 * tj + ocol);
+    f32x4 acc;
+    if (first) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = lab(I, J, 16 * ti + orow + r) == gc ? 1.f : 0.f;
+    } else {
+        acc = tile16(L.Vb[jj] + 16 * ti * kLd, kLd, false, L.Ujf[jj] + 16 * tj, kLd);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        V[(int64_t)lab(I, J, 16 * ti + orow + r) * Mp + gc] = acc[r];
+        L.Vo[jj][(16 * ti + orow + r) * kLd + 16 * tj + ocol] = acc[r];
+    }
+}
+
 // The iteration of one participating workgroup w (see the file comment).
 template <bool kLocal>
 __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
@@ -394,24 +734,7 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
     long long tprev_ = now_ticks();
     long long prof_[16] = {0};
 #endif
-
-    // Roles in the inner steps: threads 0..119 rotate the 2x2 blocks (bk, bl),
-    // bk < bl, and compute the next pivots' rotations; threads 128..143 write
-    // the pivots back; threads 256..511 rotate the columns of U.
-    int bk = 0, bl = 1;
-    if (tid < kUpper) {
-        int e = tid, k = 0;
-        while (e >= kB - 1 - k) { e -= kB - 1 - k; ++k; }
-        bk = k;
-        bl = k + 1 + e;
-    }
-    const int ptid = tid < kUpper ? tid : 0;
-    const bool uthr = tid >= 256;
-    const int uk = tid & 15, ur = (tid >> 4) & 15;   // U task: pair uk, rows ur and ur + 16
-    // Tile products: wave w takes output tile (ti, tj) of column pair wjj.
-    const int wjj = wave >> 2, ti = (wave >> 1) & 1, tj = wave & 1;
     const int orow = 4 * (lane >> 4), ocol = lane & 15;
-    f32x4 vacc = {0.f, 0.f, 0.f, 0.f};
     long long mycnt = 0, cnt_prev = 0;
     double fro2 = 0.0, off2 = 0.0, lim2 = 0.0;
     float floor_abs = 0.f;
@@ -435,9 +758,9 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
         rr_where(nb, up, I, q1, o1);
         rr_where(nb, up, J, q2, o2);
 
-        // ---- operands of step t: D = A_t[pair x, pair x] -------------------------
+        // ---- A: operands of step t ---------------------------------------------
         if (t == 0) {
-            // A_0 = C (padded with zeros), U_{-1} = I, V_0 = I.
+            // A_0 = C (padded with zeros): D and the R tiles straight from C.
             int nonfin = 0;
             for (int e = tid; e < 1024; e += kThreads) {
                 const int r = e >> 5, c = e & 31;
@@ -453,11 +776,6 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
                 }
             }
             if (nonfin) atomicOr(&L.st_bad, 1);
-            {
-                const int gc = lab(Kc[wjj], Lc[wjj], 16 * tj + ocol);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) vacc[r] = lab(I, J, 16 * ti + orow + r) == gc ? 1.f : 0.f;
-            }
         } else {
             const int hb = ((t - 1) & 1) * nb;              // block-row offset of H_{t-1}
             const int uoff = ((t - 1) & 1) * P;             // U index offset of step t-1
@@ -485,117 +803,88 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
                 commit_u(L.Uj[jj], L.Ujf[jj], vUj[jj]);
                 commit_tile(L.Vb[jj], vVb[jj]);
             }
-            __syncthreads();
-            PROF(0);
-            // Columns of block I from (T1, U1), of block J from (T2, U2): waves 0..3.
-            if (wave < 4) {
-                const double *Ta = tj == 0 ? L.T1 : L.T2;
-                const double *Ua = (tj == 0 ? L.U1 : L.U2) + 16 * (tj == 0 ? o1 : o2);
-                const f64x4 dacc = tile16d(Ta + 16 * ti * kLdd, kLdd, false, Ua, kLdd);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) L.D[(16 * ti + orow + r) * kLd + 16 * tj + ocol] = (float)dacc[r];
-            }
         }
-
-        // ---- inner rotations on D -> Ui ---------------------------------------------
-        const int s0 = (u == 0) ? 0 : kC0;
-        for (int e = tid; e < 1024; e += kThreads) {
-            const int r = e >> 5, c = e & 31;
-            L.Ui[r * kLdd + c] = r == c ? 1.0 : 0.0;
-        }
-        if (tid == 0) L.st_cnt = 0;
+        if (tid == 0) L.pub = 0;
         __syncthreads();
-        if (tid < 16) {
-            const int p = L.sp[s0][tid], q = L.sq[s0][tid];
-            make_rec(L, s0 & 1, tid, L.D[p * kLd + p], L.D[q * kLd + q], L.D[sym(p, q)], floor_abs, fp64);
+        PROF(0);
+
+        // ---- B: D (waves 0-3), the first column pair's R (waves 4-7) -----------
+        {
+            const int ti = (wave >> 1) & 1, tj = wave & 1;
+            if (wave < 4) {
+                if (t > 0) {
+                    // Columns of block I from (T1, U1), of block J from (T2, U2).
+                    const double *Ta = tj == 0 ? L.T1 : L.T2;
+                    const double *Ua = (tj == 0 ? L.U1 : L.U2) + 16 * (tj == 0 ? o1 : o2);
+                    const f64x4 dacc = tile16d(Ta + 16 * ti * kLdd, kLdd, false, Ua, kLdd);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) L.D[(16 * ti + orow + r) * kLd + 16 * tj + ocol] = (float)dacc[r];
+                }
+            } else if (t > 0) {
+                r_tile(L, 0, ti, tj);
+            }
         }
         __syncthreads();
         PROF(1);
-        int my_applied = 0;
-        for (int s = s0; s < kNS; ++s) {
-            const int ps = s & 1;
-            const bool intra = s < kC0;
-            const int c = s - kC0;   // cross step index
-            if (tid < kUpper) {
-                int pk, qk, pl, ql;
-                if (intra) {
-                    pk = L.sp[s][bk]; qk = L.sq[s][bk]; pl = L.sp[s][bl]; ql = L.sq[s][bl];
-                } else {
-                    pk = bk; qk = kB + ((bk + c) & 15); pl = bl; ql = kB + ((bl + c) & 15);
-                }
-                // Rows p_k, q_k by pair bk's rotation, columns p_l, q_l by
-                // pair bl's, in place. Every LDS read of the step first.
-                const float2 rk = L.rcf[ps][bk], rl = L.rcf[ps][bl];
-                const float2 dk = L.rdg[ps][bk], dl = L.rdg[ps][bl];
-                const int i00 = sym(pk, pl), i01 = sym(pk, ql), i10 = sym(qk, pl), i11 = sym(qk, ql);
-                const float x00 = L.D[i00], x01 = L.D[i01], x10 = L.D[i10], x11 = L.D[i11];
-                unsigned pa = 0xffu, pb = 0xffu;
-                if (intra) {
-                    pa = L.prodA[s][ptid];
-                    pb = L.prodB[s][ptid];
-                } else if (c < kB - 1) {
-                    // Cross steps: block (k, k+1) produces pair k (entry
-                    // (p_k, q_l)), block (0, 15) pair 15 (entry (q_k, p_l)).
-                    if (bl == bk + 1) pa = 1u | ((unsigned)bk << 2);
-                    else if (bk == 0 && bl == kB - 1) pa = 2u | ((unsigned)(kB - 1) << 2);
-                }
-                const float y00 = rk.x * x00 - rk.y * x10, y10 = rk.y * x00 + rk.x * x10;
-                const float y01 = rk.x * x01 - rk.y * x11, y11 = rk.y * x01 + rk.x * x11;
-                const float z00 = rl.x * y00 - rl.y * y01, z01 = rl.y * y00 + rl.x * y01;
-                const float z10 = rl.x * y10 - rl.y * y11, z11 = rl.y * y10 + rl.x * y11;
-                // A next-step pivot among the four entries: its rotation, from
-                // the entry and the two diagonal entries after this step.
-                for (int h = 0; h < 2; ++h) {
-                    const unsigned pr = h == 0 ? pa : pb;
-                    if (pr != 0xffu) {
-                        const int e = pr & 3, kn = pr >> 2;
-                        const float z = e == 0 ? z00 : (e == 1 ? z01 : (e == 2 ? z10 : z11));
-                        const int a = e < 2 ? pk : qk, b = (e & 1) ? ql : pl;
-                        const float da = e < 2 ? dk.x : dk.y, db = (e & 1) ? dl.y : dl.x;
-                        const bool lo = a < b;
-                        make_rec(L, ps ^ 1, kn, lo ? da : db, lo ? db : da, z, floor_abs, fp64);
-                    }
-                }
-                L.D[i00] = z00;
-                L.D[i01] = z01;
-                L.D[i10] = z10;
-                L.D[i11] = z11;
-            } else if (tid >= 128 && tid < 144) {
-                const int k = tid - 128;
-                const int p = intra ? L.sp[s][k] : k, q = intra ? L.sq[s][k] : kB + ((k + c) & 15);
-                L.D[sym(p, q)] = L.rpv[ps][k];
-                my_applied += L.rap[ps][k];
-            } else if (uthr) {
-                // Ui <- Ui P_s: columns p, q of pair uk in rows ur and ur + 16.
-                const int up_ = intra ? L.sp[s][uk] : uk, uq_ = intra ? L.sq[s][uk] : kB + ((uk + c) & 15);
-                const float2 ucs = L.rcf[ps][uk];
-                const double ua0 = L.Ui[ur * kLdd + up_], ub0 = L.Ui[ur * kLdd + uq_];
-                const double ua1 = L.Ui[(ur + 16) * kLdd + up_], ub1 = L.Ui[(ur + 16) * kLdd + uq_];
-                const double2 cs = rot64(ucs);
-                L.Ui[ur * kLdd + up_] = cs.x * ua0 - cs.y * ub0;
-                L.Ui[ur * kLdd + uq_] = cs.y * ua0 + cs.x * ub0;
-                L.Ui[(ur + 16) * kLdd + up_] = cs.x * ua1 - cs.y * ub1;
-                L.Ui[(ur + 16) * kLdd + uq_] = cs.y * ua1 + cs.x * ub1;
-            }
-            __syncthreads();
-        }
-        if (my_applied) atomicAdd(&L.st_cnt, my_applied);
-        PROF(2);
 
-        // ---- R = A_t[pair x, pair j], H_t = Ui^T R, V_t, partial sums ------------------
-        if (t > 0 && wjj < ncg) {
-            const f64x4 racc = tile16d(L.Tj[wjj] + 16 * ti * kLdd, kLdd, false, L.Uj[wjj] + 16 * tj, kLdd);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) L.R[wjj][(16 * ti + orow + r) * kLdd + 16 * tj + ocol] = racc[r];
-            vacc = tile16(L.Vb[wjj] + 16 * ti * kLd, kLd, false, L.Ujf[wjj] + 16 * tj, kLd);
-        }
-        if (wjj < ncg) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                A.V[(int64_t)lab(I, J, 16 * ti + orow + r) * Mp + lab(Kc[wjj], Lc[wjj], 16 * tj + ocol)] = vacc[r];
+        // ---- C: inner rotations (wave 0), U (waves 1-2), other tiles (waves 3-7) --
+#ifdef BJ_PROFILE
+        const long long tC = now_ticks();
+#endif
+        if (wave == 0) {
+            int napp = fp64 ? inner_all<true>(L, u == 0, floor_abs) : inner_all<false>(L, u == 0, floor_abs);
+            napp = wave_sum_int(napp);
+            if (lane == 0) L.st_cnt = napp;
+#ifdef BJ_PROFILE
+            if (lane == 0) prof_[5] += now_ticks() - tC;
+#endif
+        } else if (wave <= 2) {
+            const int h = wave - 1;
+            bool ok;
+            if (u == 0) {
+                ok = u_phase<8>(L, 0, true, h) && u_phase<4>(L, 8, false, h) && u_phase<2>(L, 12, false, h) &&
+                     u_phase<1>(L, 14, false, h) && u_phase<16>(L, 15, false, h);
+            } else {
+                ok = u_phase<16>(L, 0, true, h);
+            }
+            if (!ok && lane == 0) L.st_fail = 1;
+#ifdef BJ_PROFILE
+            if (lane == 0) L.prof_w[wave] = now_ticks() - tC;
+#endif
+        } else {
+            // Tasks: 0-3 the second column pair's R tiles (with their sums),
+            // 4-7 the sums of the first pair's R tiles, 8-15 V tiles.
+            for (int task = wave - 3; task < 16; task += 5) {
+                if (task < 4) {
+                    if (ncg > 1) {
+                        if (t > 0) r_tile(L, 1, task >> 1, task & 1);
+                        r_sums(L, 1, task >> 1, task & 1, I, J, Kc[1], Lc[1]);
+                    }
+                } else if (task < 8) {
+                    r_sums(L, 0, (task >> 1) & 1, task & 1, I, J, Kc[0], Lc[0]);
+                } else {
+                    const int vt = task - 8, jj = vt >> 2;
+                    if (jj < ncg) v_task(L, A.V, Mp, jj, (vt >> 1) & 1, vt & 1, t == 0, I, J, Kc[jj], Lc[jj]);
+                }
+            }
+#ifdef BJ_PROFILE
+            if (lane == 0) L.prof_w[wave] = now_ticks() - tC;
+#endif
         }
         __syncthreads();
+#ifdef BJ_PROFILE
+        if (tid == 0) {
+            prof_[6] += L.prof_w[1] > L.prof_w[2] ? L.prof_w[1] : L.prof_w[2];
+            long long mx = 0;
+            for (int v = 3; v < 8; ++v) mx = L.prof_w[v] > mx ? L.prof_w[v] : mx;
+            prof_[7] += mx;
+        }
+#endif
+        PROF(2);
+
+        // ---- D: H_t = U_{t,x}^T R, U_{t,x}, partial sums -----------------------
         {
+            const int wjj = wave >> 2, ti = (wave >> 1) & 1, tj = wave & 1;
             if (wjj < ncg) {
                 const f64x4 hacc = tile16d(L.Ui + 16 * ti, kLdd, true, L.R[wjj] + 16 * tj, kLdd);
                 double *Hd = A.H + (int64_t)(t & 1) * Mp * Mp;
@@ -603,31 +892,21 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
                 for (int r = 0; r < 4; ++r)
                     Hd[(int64_t)lab(I, J, 16 * ti + orow + r) * Mp + lab(Kc[wjj], Lc[wjj], 16 * tj + ocol)] = hacc[r];
             }
-            double so = 0.0, st = 0.0;
-            for (int jj = 0; jj < ncg; ++jj) {
-                for (int e = tid; e < 1024; e += kThreads) {
-                    const int r = e >> 5, c = e & 31;
-                    const double v = L.R[jj][r * kLdd + c];
-                    st += v * v;
-                    if (lab(I, J, r) != lab(Kc[jj], Lc[jj], c)) so += v * v;
-                }
-            }
-            so = wave_sum(so);
-            st = wave_sum(st);
-            if (lane == 0) { L.red[0][wave] = so; L.red[1][wave] = st; }
         }
         if (g == 0) {
             const int r = tid >> 4, c = (tid & 15) * 2;
             double *Ud = A.U + ((int64_t)(t & 1) * P + x) * 1024;
             *reinterpret_cast<double2 *>(&Ud[r * 32 + c]) = make_double2(L.Ui[r * kLdd + c], L.Ui[r * kLdd + c + 1]);
         }
-        __syncthreads();
         if (tid == 0) {
             BjPart pp;
-            pp.off = ((L.red[0][0] + L.red[0][1]) + (L.red[0][2] + L.red[0][3])) +
-                     ((L.red[0][4] + L.red[0][5]) + (L.red[0][6] + L.red[0][7]));
-            pp.tot = ((L.red[1][0] + L.red[1][1]) + (L.red[1][2] + L.red[1][3])) +
-                     ((L.red[1][4] + L.red[1][5]) + (L.red[1][6] + L.red[1][7]));
+            double so = 0.0, st = 0.0;
+            for (int e = 0; e < 4 * ncg; ++e) {
+                so += L.red[0][e];
+                st += L.red[1][e];
+            }
+            pp.off = so;
+            pp.tot = st;
             pp.rot = g == 0 ? mycnt : 0;
             pp.pad = 0;
             A.part[(t & 1) * G + w] = pp;
@@ -641,7 +920,7 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
         failed = L.st_fail;
         if (failed || bad) break;
 
-        // ---- stop rule at the start of a sweep -------------------------------------------
+        // ---- stop rule at the start of a sweep -------------------------------------
         if (u == 0) {
             double so = 0.0, st = 0.0;
             long long cnt = 0;
@@ -677,13 +956,7 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
                 const int r = e >> 5, c = e & 31;
                 const int gr = lab(I, J, r), gc = lab(Kc[jj], Lc[jj], c);
                 if (gr == gc && gr < m) A.lam_u[gr] = L.R[jj][r * kLdd + c];
-            }
-        }
-        if (wjj < ncg) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gr = lab(I, J, 16 * ti + orow + r), gc = lab(Kc[wjj], Lc[wjj], 16 * tj + ocol);
-                if (gr < m && gc < m) A.VuT[(int64_t)gc * A.nvu + gr] = vacc[r];
+                if (gr < m && gc < m) A.VuT[(int64_t)gc * A.nvu + gr] = L.Vo[jj][r * kLd + c];
             }
         }
     }
@@ -714,48 +987,7 @@ __global__ __launch_bounds__(kThreads) void bj_kernel(BjArgs A, int res)
     const int w = (int)(blockIdx.x >> 3);
     const int tid = threadIdx.x;
     const int P = A.nb / 2, G = P * A.Q;
-
-    // Inner schedule tables: steps 0..14 round-robin within each block, 15
-    // the first cross step.
-    for (int e = tid; e < (kC0 + 1) * 16; e += kThreads) {
-        const int s = e >> 4, k = e & 15;
-        int p, q;
-        if (s < kC0) {
-            const int kk = k & 7, off = (k >> 3) * kB;
-            p = rr_pos(kB, s, kk) + off;
-            q = rr_pos(kB, s, kB - 1 - kk) + off;
-        } else {
-            p = k;
-            q = kB + k;
-        }
-        if (p > q) { const int tt = p; p = q; q = tt; }
-        L.sp[s][k] = (unsigned char)p;
-        L.sq[s][k] = (unsigned char)q;
-        L.pid[s][p] = (unsigned char)k;
-        L.pid[s][q] = (unsigned char)k;
-    }
-    if (tid == 0) { L.st_bad = 0; L.st_fail = 0; L.st_cnt = 0; }
-    __syncthreads();
-    if (tid < kUpper) {
-        int e = tid, bk = 0;
-        while (e >= kB - 1 - bk) { e -= kB - 1 - bk; ++bk; }
-        const int bl = bk + 1 + e;
-        for (int s = 0; s < kC0; ++s) {
-            unsigned char a = 0xff, b = 0xff;
-            const int pk = L.sp[s][bk], qk = L.sq[s][bk], pl = L.sp[s][bl], ql = L.sq[s][bl];
-            const int ii[4] = {pk, pk, qk, qk}, jj[4] = {pl, ql, pl, ql};
-            for (int h = 0; h < 4; ++h) {
-                const int kn = L.pid[s + 1][ii[h]];
-                if (kn == L.pid[s + 1][jj[h]]) {
-                    const unsigned char v = (unsigned char)(h | (kn << 2));
-                    if (a == 0xff) a = v;
-                    else b = v;
-                }
-            }
-            L.prodA[s][tid] = a;
-            L.prodB[s][tid] = b;
-        }
-    }
+    if (tid == 0) { L.st_bad = 0; L.st_fail = 0; L.st_cnt = 0; L.pub = 0; }
 
     // XCD check: every participant publishes its XCD id, one device-scope
     // barrier, then the same decision everywhere.

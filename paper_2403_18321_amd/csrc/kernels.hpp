@@ -100,7 +100,7 @@ __host__ __device__ inline size_t bj_workspace_bytes(int m)
            2 * (size_t)P * P * 32 + 256 * sizeof(unsigned int);
 }
 // Band counts from which pca_jacobi_eigh takes the block-cyclic form by default.
-constexpr int kBjMinBands = 224;
+constexpr int kBjMinBands = 96;
 // Workgroups of the block-cyclic form (all on one XCD) and column pairs each.
 constexpr int kBjMaxGroups = 32;
 constexpr int kBjMaxColPairs = 2;

@@ -41,7 +41,7 @@ def test_stream_matches_single_pipeline(pca, chain):
     Yd = [torch.from_numpy(c).cuda() for c in cubes]
     ref = []
     for Y in Yd:
-        r = pca.PCAPipeline(n, m, k, "bf16x3").forward(Y)
+        r = pca.PCAPipeline(n, m, k, "bf16x3", jacobi="one_cu").forward(Y)   # the stream's eigen-solver form
         ref.append([host(t).copy() for t in (r.mean, r.eigvals, r.V, r.Q)])
     ps = pca.PCAStream(n, m, k, "bf16x3", depth=2, chain=chain)
     # Seven submissions over two slots: every slot is reused while the other
@@ -71,7 +71,7 @@ def test_stream_overlapped_results(pca):
     ps.join()
     torch.cuda.synchronize()
     for i, (Y, r) in enumerate(zip(Yd, res)):
-        s = pca.PCAPipeline(n, m, k, "f32").forward(Y)
+        s = pca.PCAPipeline(n, m, k, "f32", jacobi="one_cu").forward(Y)
         assert np.array_equal(host(s.eigvals), host(r.eigvals)), i
         assert np.array_equal(host(s.Q), host(r.Q)), i
 
