@@ -216,6 +216,26 @@ pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t 
                            int32_t flags, float *eigvals, float *V, pca_info *info,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* Bytes of device memory that pca_jacobi_eigh_noalloc holds on each GPU it
+ * runs on (until the process ends). */
+#define PCA_NOALLOC_SCRATCH_BYTES (12u << 20)
+
+/*
+ * pca_jacobi_eigh for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same calls and results, with the workspace taken from a fixed
+ * PCA_NOALLOC_SCRATCH_BYTES array in the library's device memory instead of
+ * an argument. It allocates and frees nothing. Requests whose workspace
+ * (pca_workspace_size(PCA_OP_JACOBI, ...)) exceeds that size return
+ * PCA_ERR_WORKSPACE (at 256 bands, max_sweeps up to about 40 fit). The array
+ * is shared by every call on one GPU: calls that overlap in time on one GPU
+ * (other streams, other host threads) race and must not be issued; calls on
+ * one stream run in order and are safe. Arguments and results as for
+ * pca_jacobi_eigh; PCA_ERR_HIP if the array's address cannot be obtained.
+ */
+pca_status pca_jacobi_eigh_noalloc(const float *C, int32_t n_bands, double tol, int32_t max_sweeps, int32_t flags,
+                                   float *eigvals, float *V, pca_info *info, void *stream);
+
 /*
  * Projection onto the first k eigenvectors (Algorithm 1, lines 5-6):
  *   Q[p, i] = sum_b (Y[p, b] - mean[b]) V[b, i],  i < k.

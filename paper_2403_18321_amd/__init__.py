@@ -31,6 +31,7 @@ from ._lib import (  # noqa: F401
     pca_center,
     pca_covariance,
     pca_jacobi_eigh,
+    pca_jacobi_eigh_noalloc,
     pca_project,
     pca_workspace_size,
     read_info,

@@ -33,7 +33,8 @@ INFO_BYTES = struct.calcsize(INFO_FORMAT)
 INFO_FIELDS = ("sweeps", "converged", "nonfinite", "floor_hit", "off_rel", "rotations", "steps", "n_bands")
 
 EXPORTS = ("pca_status_string", "pca_workspace_size", "pca_center", "pca_covariance",
-           "pca_jacobi_eigh", "pca_project", "pca_backward", "pca_batched_workspace_size", "pca_batched")
+           "pca_jacobi_eigh", "pca_jacobi_eigh_noalloc", "pca_project", "pca_backward", "pca_batched_workspace_size",
+           "pca_batched")
 
 
 class PCACube(ctypes.Structure):
@@ -79,6 +80,8 @@ def _lib() -> ctypes.CDLL:
                                        _sz, _vp]
         lib.pca_jacobi_eigh.restype = ctypes.c_int
         lib.pca_jacobi_eigh.argtypes = [_vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
+        lib.pca_jacobi_eigh_noalloc.restype = ctypes.c_int
+        lib.pca_jacobi_eigh_noalloc.argtypes = [_vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _vp]
         lib.pca_project.restype = ctypes.c_int
         lib.pca_project.argtypes = [_vp, ctypes.c_int, _i64, _i32, _i64, _vp, _vp, _i32, _vp, _vp]
         lib.pca_batched_workspace_size.restype = ctypes.c_int
@@ -179,6 +182,18 @@ def pca_jacobi_eigh(C, eigvals, V, tol: float, max_sweeps: int, fp64_angles: boo
     _check("pca_jacobi_eigh", _lib().pca_jacobi_eigh(_ptr(C), m, float(tol), int(max_sweeps), flags,
                                                      _ptr(eigvals), _ptr(V), _ptr(info), _ptr(ws), ws.numel(),
                                                      _stream()))
+
+
+def pca_jacobi_eigh_noalloc(C, eigvals, V, tol: float, max_sweeps: int, fp64_angles: bool = True, info=None,
+                            overlap: bool = False, form: str = "auto"):
+    """pca_jacobi_eigh with the library's own device scratch array as the
+    workspace (no allocation by the library or here)."""
+    m = C.shape[0]
+    flags = ((PCA_JACOBI_FP64_ANGLES if fp64_angles else 0) | (PCA_JACOBI_OVERLAP_REPLAY if overlap else 0)
+             | JACOBI_FORMS[form])
+    _check("pca_jacobi_eigh_noalloc",
+           _lib().pca_jacobi_eigh_noalloc(_ptr(C), m, float(tol), int(max_sweeps), flags, _ptr(eigvals), _ptr(V),
+                                          _ptr(info), _stream()))
 
 
 def pca_project(Y, mean, V, k: int, Q, layout: str = "bip"):

@@ -3,8 +3,14 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 #include "pca.h"
+
+// Device memory of pca_jacobi_eigh_noalloc: one copy per GPU, held until the
+// process ends. Host code takes its address only through scratch_ptr().
+static __device__ __align__(256) unsigned char scratch[PCA_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -77,6 +83,24 @@ pca_status batch_plan(const pca_cube *cubes, int32_t n_cubes, int32_t max_sweeps
     if (cov_chunk) *cov_chunk = chunk;
     if (proj_tiles) *proj_tiles = tiles;
     return PCA_OK;
+}
+
+// The address of this device's copy of `scratch` (hipGetSymbolAddress once
+// per device, with that device current), or nullptr if it cannot be had.
+constexpr int kMaxDevices = 64;
+void *scratch_ptr()
+{
+    static std::mutex mu;
+    static void *ptr[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        ptr[dev] = p;
+    }
+    return ptr[dev];
 }
 
 }  // namespace
@@ -200,6 +224,16 @@ pca_status pca_jacobi_eigh(const float *C, int32_t n_bands, double tol, int32_t 
     }
     return hip_status(pca::launch_jacobi(C, n_bands, tol, max_sweeps, fp64, (flags & PCA_JACOBI_OVERLAP_REPLAY) ? 1 : 0,
                                          plan, lam_u, rlog, Vu, info_ws, eigvals, V, info, st));
+}
+
+pca_status pca_jacobi_eigh_noalloc(const float *C, int32_t n_bands, double tol, int32_t max_sweeps, int32_t flags,
+                                   float *eigvals, float *V, pca_info *info, void *stream)
+{
+    if (n_bands < 2 || n_bands > pca::kMaxBands || max_sweeps < 0 || max_sweeps > 100000) return PCA_ERR_ARG;
+    if (jac_ws(pca::jac_plan(n_bands, max_sweeps)) > PCA_NOALLOC_SCRATCH_BYTES) return PCA_ERR_WORKSPACE;
+    void *ws = scratch_ptr();
+    if (!ws) return PCA_ERR_HIP;
+    return pca_jacobi_eigh(C, n_bands, tol, max_sweeps, flags, eigvals, V, info, ws, PCA_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,

@@ -93,6 +93,14 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert so.pca_jacobi_eigh(fake, 300, 1e-6, 10, 1, fake, fake, null, fake, 1 << 20, null) == ARG
     assert so.pca_jacobi_eigh(fake, 8, 1e-6, 10, 1, fake, fake, null, ctypes.c_void_p(4100), 1 << 20,
                               null) == ARG
+    # The no-allocation form: a request larger than its fixed device array,
+    # and bad sizes, are refused before any device call.
+    na = so.pca_jacobi_eigh_noalloc
+    na.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert na(fake, 256, 1e-6, 100000, 1, fake, fake, null, null) == lib.PCA_ERR_WORKSPACE
+    assert na(fake, 300, 1e-6, 10, 1, fake, fake, null, null) == ARG
+    assert na(fake, 8, 1e-6, -1, 1, fake, fake, null, null) == ARG
     # Projection: k out of range.
     assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 0, fake, null) == ARG
     assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 9, fake, null) == ARG
