@@ -74,27 +74,24 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 // ---- pass 0: the shift row ------------------------------------------------
 //
 // s_b = mean of a sample of the pixels of band b: every pixel up to
-// kShiftSample of them, else kShiftRuns runs of 32 consecutive pixels spread
-// evenly over the cube, added in float64 in a fixed order. Any shift gives
-// the same covariance in exact arithmetic (pass 2 removes it exactly); one
-// close to the band mean keeps the shifted values small whatever a single
-// pixel holds (a dead or hot detector column at the start of every chunk,
-// for one), and with them the rounding of the products, which the
-// split-bfloat16 forms feel most. uint16 cubes round s to an integer so that
-// the row can also be held in the cube's own type; float32 cubes keep it as
-// it is. Shift area: float32 s[256], then the cube-type row [256].
-constexpr int kShiftRuns = 32;
-constexpr int kShiftSample = 32 * kShiftRuns;   // 1024 pixels
+// kShiftSample of them, else kShiftSample pixels an odd stride apart (an odd
+// stride runs through every image column of a power-of-two-wide scene, so no
+// single detector column is over-represented), added in float64 in a fixed
+// order. Any shift gives the same covariance in exact arithmetic (pass 2
+// removes it exactly); one close to the band mean keeps the shifted values
+// small whatever a single pixel holds (a dead or hot detector column at the
+// start of every chunk, for one), and with them the rounding of the
+// products, which the split-bfloat16 forms feel most. uint16 cubes round s to
+// an integer so that the row can also be held in the cube's own type; float32
+// cubes keep it as it is. Shift area: float32 s[256], then the cube-type row
+// [256].
+constexpr int kShiftSample = 256;
 constexpr int kShiftThreads = 256;              // one 32-band block a workgroup
-
-__device__ inline int64_t shift_pixel(int64_t n, int i)
-{
-    return n <= kShiftSample ? (int64_t)i : (int64_t)(i >> 5) * n / kShiftRuns + (i & 31);
-}
 
 // Band block bb (bands 32 bb .. 32 bb + 31) of the shift row. Band-interleaved
 // cubes: the 32 lanes of a group read one sampled pixel's 32 bands;
-// band-sequential cubes: 8 lanes read 8 consecutive sampled pixels of a band.
+// band-sequential cubes: 8 lanes read 8 sampled pixels of a band. Every
+// thread issues all of its 32 loads before adding them.
 template <typename T>
 __device__ void cov_shift_body(const T *__restrict__ Y, int64_t n, int m, int64_t ld, bool bsq, int bb,
                                float *__restrict__ srow)
@@ -102,16 +99,22 @@ __device__ void cov_shift_body(const T *__restrict__ Y, int64_t n, int m, int64_
     __shared__ double red[32][9];
     const int tid = threadIdx.x;
     const int ns = n < kShiftSample ? (int)n : kShiftSample;
+    int64_t stride = (n - 1) / (ns - 1);
+    if (stride > 1 && (stride & 1) == 0) --stride;
     const int bl = bsq ? tid >> 3 : tid & 31;
     const int i0 = bsq ? tid & 7 : tid >> 5;
     const int b = 32 * bb + bl;
-    double a = 0.0;
-    if (b < m) {
-        const T *base = bsq ? Y + (int64_t)b * ld : Y + b;
-        const int64_t step = bsq ? 1 : ld;
-#pragma unroll 8
-        for (int i = i0; i < ns; i += 8) a += (double)load_elem(base + shift_pixel(n, i) * step);
+    float v[kShiftSample / 8];
+    const T *base = bsq ? Y + (int64_t)(b < m ? b : 0) * ld : Y + (b < m ? b : 0);
+    const int64_t step = bsq ? 1 : ld;
+#pragma unroll
+    for (int j = 0; j < kShiftSample / 8; ++j) {
+        const int i = i0 + 8 * j;
+        v[j] = (b < m && i < ns) ? load_elem(base + (int64_t)i * stride * step) : 0.f;
     }
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < kShiftSample / 8; ++j) a += (double)v[j];
     red[bl][i0] = a;
     __syncthreads();
     if (tid < 32) {

@@ -521,9 +521,6 @@ __device__ __attribute__((noinline)) int inner_phase(Smem &L, int s0, float floo
     rl = L.rec[s0][l];
     for (int c = 0; c < H; ++c) {
         const int s = s0 + c;
-        // Slot 0 first: the values that leave this 16-lane row for the next
-        // step (H = 8, 16) are sent while slots 1-3 are updated.
-        float x1 = 0.f, x2 = 0.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float ck = rk[r].x, sk = rk[r].y;
@@ -533,10 +530,6 @@ __device__ __attribute__((noinline)) int inner_phase(Smem &L, int s0, float floo
             aIJ[r] = rl.y * yII + rl.x * yIJ;
             aJI[r] = rl.x * yJI - rl.y * yJJ;
             aJJ[r] = rl.y * yJI + rl.x * yJJ;
-            if (r == 0 && H >= 8 && c < H - 1) {
-                x1 = lane_take(aJI[0], 16 * kg_row + l);
-                x2 = lane_take(aJJ[0], 16 * kg_row + ph_next<H>(l));
-            }
         }
         if (c == H - 1) break;
         // The next step's rotation of pair 4 kg + rp: its pivot is this
@@ -555,6 +548,7 @@ __device__ __attribute__((noinline)) int inner_phase(Smem &L, int s0, float floo
             }
         }
         publish(L, s + 2);
+        // The next step's records (read while the values below move).
 #pragma unroll
         for (int r = 0; r < 4; ++r) rk[r] = L.rec[s + 1][4 * kg + r];
         rl = L.rec[s + 1][l];
@@ -564,17 +558,20 @@ __device__ __attribute__((noinline)) int inner_phase(Smem &L, int s0, float floo
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int kn = ph_next<H>(r) & 3;   // slot of next(4 kg + r) when it stays in this lane
-            aIJ[r] = col_next<H>(aIJ[r], l);
             if (H >= 8 && r == 3) {
-                nJI[r] = x1;
-                nJJ[r] = x2;
+                nJI[r] = lane_take(aJI[0], 16 * kg_row + l);
+                nJJ[r] = lane_take(aJJ[0], 16 * kg_row + ph_next<H>(l));
             } else {
                 nJI[r] = aJI[kn];
                 nJJ[r] = col_next<H>(aJJ[kn], l);
             }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) { aJI[r] = nJI[r]; aJJ[r] = nJJ[r]; }
+        for (int r = 0; r < 4; ++r) {
+            aIJ[r] = col_next<H>(aIJ[r], l);
+            aJI[r] = nJI[r];
+            aJJ[r] = nJJ[r];
+        }
     }
     if constexpr (kWrite) {
         const int c0 = ph_local<H>(l), c1 = ph_local<H>(16 + ph_sigma<H>(H - 1, l));
