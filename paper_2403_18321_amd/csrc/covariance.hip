@@ -74,47 +74,71 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 // ---- pass 0: the shift row ------------------------------------------------
 //
 // s_b = mean of a sample of the pixels of band b: every pixel up to
-// kShiftSample of them, else kShiftSample pixels an odd stride apart (an odd
-// stride runs through every image column of a power-of-two-wide scene, so no
-// single detector column is over-represented), added in float64 in a fixed
-// order. Any shift gives the same covariance in exact arithmetic (pass 2
-// removes it exactly); one close to the band mean keeps the shifted values
+// kShiftSample of them, else kShiftRuns runs of 32 pixels spread evenly over
+// the cube, the pixels of a run an odd stride apart (an odd stride runs
+// through every image column of a power-of-two-wide scene, so no single
+// detector column is over-represented; a run stays within a few pages, so
+// the sample costs few address-translation misses), added in float64 in a
+// fixed order. Any shift gives the same covariance in exact arithmetic (pass
+// 2 removes it exactly); one close to the band mean keeps the shifted values
 // small whatever a single pixel holds (a dead or hot detector column at the
 // start of every chunk, for one), and with them the rounding of the
 // products, which the split-bfloat16 forms feel most. uint16 cubes round s to
 // an integer so that the row can also be held in the cube's own type; float32
 // cubes keep it as it is. Shift area: float32 s[256], then the cube-type row
 // [256].
-constexpr int kShiftSample = 256;
+constexpr int kShiftRuns = 8;
+constexpr int kShiftSample = 32 * kShiftRuns;   // 256 pixels
 constexpr int kShiftThreads = 256;              // one 32-band block a workgroup
 
 // Band block bb (bands 32 bb .. 32 bb + 31) of the shift row. Band-interleaved
 // cubes: the 32 lanes of a group read one sampled pixel's 32 bands;
-// band-sequential cubes: 8 lanes read 8 sampled pixels of a band. Every
-// thread issues all of its 32 loads before adding them.
+// band-sequential cubes: 8 lanes read 8 sampled pixels of a band. Sample i
+// (thread offset i0 = i mod 8, j = i / 8) of a cube of n > kShiftSample
+// pixels is pixel start(r) + (i mod 32) stride of run r = i / 32, with
+// start(r) = r n / kShiftRuns + 5 r (the small offset keeps the runs' first
+// pixels off one image column when n / kShiftRuns is a multiple of the scene
+// width) and an odd stride of at most 67, so every sample stays inside its
+// run's n / kShiftRuns pixels. Every thread issues all of its 32 loads (at
+// clamped addresses) before adding the valid ones.
 template <typename T>
-__device__ void cov_shift_body(const T *__restrict__ Y, int64_t n, int m, int64_t ld, bool bsq, int bb,
+__device__ __forceinline__ void cov_shift_body(const T *__restrict__ Y, int64_t n, int m, int64_t ld, bool bsq, int bb,
                                float *__restrict__ srow)
 {
     __shared__ double red[32][9];
     const int tid = threadIdx.x;
-    const int ns = n < kShiftSample ? (int)n : kShiftSample;
-    int64_t stride = (n - 1) / (ns - 1);
+    const bool all = n <= kShiftSample;
+    const int ns = all ? (int)n : kShiftSample;
+    const int64_t run = n / kShiftRuns;
+    const int off = run >= 32 + 36 ? 5 : 0;              // 5 r <= 35 < run - 31 stride
+    int64_t stride = off ? (run - 36) / 31 : 1;
+    stride = stride > 67 ? 67 : (stride < 1 ? 1 : stride);
     if (stride > 1 && (stride & 1) == 0) --stride;
     const int bl = bsq ? tid >> 3 : tid & 31;
     const int i0 = bsq ? tid & 7 : tid >> 5;
     const int b = 32 * bb + bl;
-    float v[kShiftSample / 8];
-    const T *base = bsq ? Y + (int64_t)(b < m ? b : 0) * ld : Y + (b < m ? b : 0);
+    const bool bok = b < m;
+    const T *base = bsq ? Y + (int64_t)(bok ? b : 0) * ld : Y + (bok ? b : 0);
     const int64_t step = bsq ? 1 : ld;
+    float v[kShiftSample / 8];
+    if (all) {
 #pragma unroll
-    for (int j = 0; j < kShiftSample / 8; ++j) {
-        const int i = i0 + 8 * j;
-        v[j] = (b < m && i < ns) ? load_elem(base + (int64_t)i * stride * step) : 0.f;
+        for (int j = 0; j < kShiftSample / 8; ++j) {
+            const int i = i0 + 8 * j;
+            v[j] = load_elem(base + (int64_t)(i < ns ? i : 0) * step);
+        }
+    } else {
+        int64_t start[kShiftRuns];
+#pragma unroll
+        for (int r = 0; r < kShiftRuns; ++r) start[r] = ((int64_t)r * n / kShiftRuns + off * r) * step;
+        const int64_t sstep = stride * step;
+#pragma unroll
+        for (int j = 0; j < kShiftSample / 8; ++j)   // sample i = i0 + 8 j: run j / 4, place 8 (j mod 4) + i0
+            v[j] = load_elem(base + start[j >> 2] + (int64_t)(8 * (j & 3) + i0) * sstep);
     }
     double a = 0.0;
 #pragma unroll
-    for (int j = 0; j < kShiftSample / 8; ++j) a += (double)v[j];
+    for (int j = 0; j < kShiftSample / 8; ++j) a += (bok && i0 + 8 * j < ns) ? (double)v[j] : 0.0;
     red[bl][i0] = a;
     __syncthreads();
     if (tid < 32) {

@@ -203,3 +203,45 @@ def test_backward_deterministic(pca):
     a = gpu_grad(pca, Y, k, ct)
     b = gpu_grad(pca, Y, k, ct)
     assert np.array_equal(a, b)
+
+
+def test_reconstruction_loss_gradient(pca):
+    """The differentiation workload's loss: L = ||X - Q V_k^T||_F^2 (X the
+    centred cube, Q and V_k from pca_autograd) on the planted 256 x 256-pixel,
+    128-band cube, k = 8. Its gradient has the closed form dL/dY = 2 X (I - V_k
+    V_k^T) (V_k spans a stationary subspace of L); the GPU gradient, which
+    goes through the projection, eigen and covariance adjoints of
+    pca_backward, is compared with it (FP64 oracle eigenvectors) and with
+    central differences of the oracle's reconstruction loss."""
+    d = synth.make_config("c5")
+    k = d["k"]
+    Y = d["Y"]
+    n, m = Y.shape
+    Yd = dev(Y).requires_grad_(True)
+    Q, lam, Vk = pca.pca_autograd(Yd, k)
+    X = Yd - Yd.mean(dim=0, keepdim=True)
+    L = ((X - Q @ Vk.t()) ** 2).sum()
+    L.backward()
+    got = host(Yd.grad).astype(np.float64)
+    ref = oracle.pca(Y, k)
+    Vr = ref["V"][:, :k]
+    closed = 2.0 * ref["X"] @ (np.eye(m) - Vr @ Vr.T)
+    err = rel(got, closed)
+    say(f"reconstruction gradient vs closed form: {err:.2e}")
+    assert err <= GRAD_TOL
+    # Central differences along unit directions D, compared with <dL/dY, D>
+    # relative to |dL/dY| (a random direction's derivative is a small part of
+    # the gradient, and the oracle's loss carries its eigensolver's
+    # convergence noise, ~1e-12 of L, which the step h must dominate).
+    rng = np.random.default_rng(1007)
+    Y64 = Y.astype(np.float64)
+    h = 1e-4 * np.abs(Y64).max()
+    gnorm = float(np.linalg.norm(got))
+    for t in range(4):
+        D = rng.standard_normal(Y.shape)
+        D /= np.linalg.norm(D)
+        fd = (oracle.reconstruction_loss(Y64 + h * D, k) - oracle.reconstruction_loss(Y64 - h * D, k)) / (2 * h)
+        an = float(np.sum(got * D))
+        e = abs(an - fd) / gnorm
+        say(f"reconstruction FD dir {t}: analytic {an:.6e} fd {fd:.6e} |dL/dY| {gnorm:.4e} rel {e:.2e}")
+        assert e <= FD_TOL

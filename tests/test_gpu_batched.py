@@ -130,6 +130,18 @@ def test_batched_workload_64_cubes(pca):
     check_against_oracle(pca, _Sub(b, sample), [cubes[i] for i in sample], [ks[i] for i in sample], "c4")
 
 
+def test_batched_full_workload_f32(pca):
+    """The 64-cube workload at its full sizes (square sides 64..512, 64..256
+    bands, k = 5) in float32: every cube against the FP64 oracle
+    (eigenvalues, well-separated eigenvectors, projections, leading
+    subspace)."""
+    cubes = synth.make_batch(64, 4000)
+    ks = [5] * len(cubes)
+    b = pca.BatchedPCA([dev(Y) for Y in cubes], ks, "f32")
+    b.run()
+    check_against_oracle(pca, b, cubes, ks, "c4 full f32")
+
+
 class _Sub:
     """View of some cubes of a BatchedPCA (for check_against_oracle)."""
 
