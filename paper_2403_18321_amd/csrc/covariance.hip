@@ -85,8 +85,11 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 // start of every chunk, for one), and with them the rounding of the
 // products, which the split-bfloat16 forms feel most. uint16 cubes round s to
 // an integer so that the row can also be held in the cube's own type; float32
-// cubes keep it as it is. Shift area: float32 s[256], then the cube-type row
-// [256].
+// cubes round it to 8 significant bits (a bfloat16 value), which keeps it
+// within 2^-9 of the sample mean and makes it an integer from 128 on, so that
+// integer-valued cubes (converted sensor counts) stay integer-valued after
+// the shift and their bfloat16 hi/lo split stays exact up to 2^16. Shift
+// area: float32 s[256], then the cube-type row [256].
 constexpr int kShiftRuns = 8;
 constexpr int kShiftSample = 32 * kShiftRuns;   // 256 pixels
 constexpr int kShiftThreads = 256;              // one 32-band block a workgroup
@@ -151,7 +154,7 @@ __device__ __forceinline__ void cov_shift_body(const T *__restrict__ Y, int64_t 
         if (bq < m) {
             const double mean = t / (double)ns;
             if constexpr (sizeof(T) == 2) sv = (float)fmin(fmax(rint(mean), 0.0), 65535.0);
-            else sv = (float)mean;
+            else sv = (float)(__bf16)(float)mean;   // 8 significant bits (see above)
         }
         srow[bq] = sv;
         if constexpr (sizeof(T) == 2) rowT[bq] = (T)(unsigned)sv;

@@ -30,15 +30,16 @@
 // Workgroup (x, g) of the P x Q grid owns, at step t, the rows of block pair
 // x of step t and the columns of the block pairs j = g, g + Q, ... of step
 // t - 1. Its eight waves split a step as follows:
-//   A. all: load the step's tiles (one round trip for all of them);
+//   A. waves 0-3 load the operands of D into LDS; waves 4-7 start the loads
+//      of the R and V operands;
 //   B. waves 0-3: D = A_t[pair x, pair x] from two tiles of H_{t-1} and two
-//      U's (float64 MFMA); waves 4-7: R = A_t[pair x, first column pair] =
-//      H_{t-1}[..] U_{t-1,j};
+//      U's (float64 MFMA); waves 4-7 put the R and V operands in LDS;
 //   C. wave 0: the inner rotations on D, held in registers (below), which
 //      publish every step's rotations in LDS; waves 1-2: U_{t,x} from those
-//      rotations in float64, one step behind; waves 3-7: the second column
-//      pair's R, V_t[pair x rows, pair j cols] = V_{t-1}[..] U_{t-1,j}
-//      (float32 MFMA), and the tiles' shares of off(A_t)^2, ||A_t||_F^2;
+//      rotations in float64, one step behind; waves 3-7: R = A_t[pair x,
+//      pair j] = H_{t-1}[..] U_{t-1,j} (float64 MFMA), V_t[pair x rows, pair
+//      j cols] = V_{t-1}[..] U_{t-1,j} (float32 MFMA), and the tiles' shares
+//      of off(A_t)^2, ||A_t||_F^2;
 //   D. all: H_t[pair x, pair j] = U_{t,x}^T R (float64 MFMA), stored with
 //      U_{t,x} and the partial sums; then a grid barrier.
 // Every workgroup of row x forms the same U_{t,x}. The stop rule (off(A)/
@@ -242,33 +243,33 @@ __device__ inline uint4 ld16(Rsrc r, int off)
     return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kLocal ? 16 : 0));
 }
 
-// Loads of one step's operand tiles are issued all at once into registers
-// (one round trip), then written to LDS.
-// 32 x 32 float64 tile of a label-space matrix (pitch ld elements): one
-// 16-byte piece per thread.
+// Loads of one step's operand tiles go into registers, then to LDS; each
+// helper takes the 16-byte piece e of its tile.
+// 32 x 32 float64 tile of a label-space matrix (pitch ld elements): pieces
+// 0..511.
 template <bool kLocal>
-__device__ inline uint4 issue_tiled(Rsrc src, int ld, int r0, int r1, int c0, int c1)
+__device__ inline uint4 issue_tiled(Rsrc src, int ld, int r0, int r1, int c0, int c1, int e)
 {
-    const int e = threadIdx.x, r = e >> 4, c = (e & 15) * 2;
+    const int r = e >> 4, c = (e & 15) * 2;
     return ld16<kLocal>(src, 8 * (lab(r0, r1, r) * ld + lab(c0, c1, c)));
 }
-__device__ inline void commit_tiled(double *dst, uint4 v)
+__device__ inline void commit_tiled(double *dst, uint4 v, int e)
 {
-    const int e = threadIdx.x, r = e >> 4, c = (e & 15) * 2;
+    const int r = e >> 4, c = (e & 15) * 2;
     const double2 d = __builtin_bit_cast(double2, v);
     dst[r * kLdd + c] = d.x;
     dst[r * kLdd + c + 1] = d.y;
 }
-// U matrix number q (32 x 32 float64, contiguous).
+// U matrix number q (32 x 32 float64, contiguous): pieces 0..511.
 template <bool kLocal>
-__device__ inline uint4 issue_u(Rsrc src, int q)
+__device__ inline uint4 issue_u(Rsrc src, int q, int e)
 {
-    const int e = threadIdx.x, r = e >> 4, c = (e & 15) * 2;
+    const int r = e >> 4, c = (e & 15) * 2;
     return ld16<kLocal>(src, 8 * (q * 1024 + r * 32 + c));
 }
-__device__ inline void commit_u(double *dst, float *dstf, uint4 v)
+__device__ inline void commit_u(double *dst, float *dstf, uint4 v, int e)
 {
-    const int e = threadIdx.x, r = e >> 4, c = (e & 15) * 2;
+    const int r = e >> 4, c = (e & 15) * 2;
     const double2 d = __builtin_bit_cast(double2, v);
     dst[r * kLdd + c] = d.x;
     dst[r * kLdd + c + 1] = d.y;
@@ -277,19 +278,28 @@ __device__ inline void commit_u(double *dst, float *dstf, uint4 v)
         dstf[r * kLd + c + 1] = (float)d.y;
     }
 }
-// 32 x 32 float32 tile of a label-space matrix: one 16-byte piece for each
-// of the first 256 threads.
+// 32 x 32 float32 tile of a label-space matrix: pieces 0..255.
 template <bool kLocal>
-__device__ inline uint4 issue_tile(Rsrc src, int ld, int r0, int r1, int c0, int c1)
+__device__ inline uint4 issue_tile(Rsrc src, int ld, int r0, int r1, int c0, int c1, int e)
 {
-    const int e = threadIdx.x & 255, r = e >> 3, c = (e & 7) * 4;
+    const int r = e >> 3, c = (e & 7) * 4;
     return ld16<kLocal>(src, 4 * (lab(r0, r1, r) * ld + lab(c0, c1, c)));
 }
-__device__ inline void commit_tile(float *dst, uint4 v)
+__device__ inline void commit_tile(float *dst, uint4 v, int e)
 {
-    if (threadIdx.x >= 256) return;
-    const int r = threadIdx.x >> 3, c = (threadIdx.x & 7) * 4;
+    const int r = e >> 3, c = (e & 7) * 4;
     *reinterpret_cast<float4 *>(&dst[r * kLd + c]) = __builtin_bit_cast(float4, v);
+}
+
+// Workgroup barrier for LDS traffic only: this wave's LDS accesses complete,
+// then s_barrier; global loads still in flight stay in flight (a
+// __syncthreads would wait for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xF | (0x3 << 14) | (0x7 << 4));   // lgkmcnt(0); vmcnt and expcnt not waited for
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 __device__ inline long long now_ticks() { return (long long)__builtin_amdgcn_s_memrealtime(); }
@@ -741,6 +751,7 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
     int Kc[kCg] = {0}, Lc[kCg] = {0};
 
     for (;; ++t) {
+        uint4 vRT[kCg][2], vRU[kCg][2], vRV[kCg];   // R and V operand pieces in flight (waves 4-7)
         const int u = t % S;
         const int up = t == 0 ? S - 1 : (t - 1) % S;
         I = rr_pos(nb, u, x);
@@ -774,51 +785,71 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
             }
             if (nonfin) atomicOr(&L.st_bad, 1);
         } else {
+            // Waves 0-3 load the operands of D (T1, T2, U1, U2: two pieces of
+            // each per thread) and put them in LDS; waves 4-7 start the loads
+            // of the R and V operands, which stay in flight across the next
+            // barrier and reach LDS while D is formed.
             const int hb = ((t - 1) & 1) * nb;              // block-row offset of H_{t-1}
             const int uoff = ((t - 1) & 1) * P;             // U index offset of step t-1
-            uint4 vTj[kCg], vUj[kCg], vVb[kCg];
-            const uint4 vT1 = issue_tiled<kLocal>(rH, Mp, hb + I, hb + J, rr_pos(nb, up, q1),
-                                                  rr_pos(nb, up, nb - 1 - q1));
-            const uint4 vT2 = issue_tiled<kLocal>(rH, Mp, hb + I, hb + J, rr_pos(nb, up, q2),
-                                                  rr_pos(nb, up, nb - 1 - q2));
-            const uint4 vU1 = issue_u<kLocal>(rU, uoff + q1);
-            const uint4 vU2 = issue_u<kLocal>(rU, uoff + q2);
+            const int e0 = tid & 255;
+            if (wave < 4) {
+                uint4 v[8];
 #pragma unroll
-            for (int jj = 0; jj < kCg; ++jj) {
-                // (a second copy of column pair 0 when there is no second)
-                vTj[jj] = issue_tiled<kLocal>(rH, Mp, hb + I, hb + J, Kc[jj], Lc[jj]);
-                vUj[jj] = issue_u<kLocal>(rU, uoff + g + (jj < ncg ? jj : 0) * Q);
-                vVb[jj] = issue_tile<kLocal>(rV, Mp, I, J, Kc[jj], Lc[jj]);
-            }
-            commit_tiled(L.T1, vT1);
-            commit_tiled(L.T2, vT2);
-            commit_u(L.U1, nullptr, vU1);
-            commit_u(L.U2, nullptr, vU2);
+                for (int h = 0; h < 2; ++h) {
+                    const int e = e0 + 256 * h;
+                    v[h] = issue_tiled<kLocal>(rH, Mp, hb + I, hb + J, rr_pos(nb, up, q1), rr_pos(nb, up, nb - 1 - q1), e);
+                    v[2 + h] = issue_tiled<kLocal>(rH, Mp, hb + I, hb + J, rr_pos(nb, up, q2),
+                                                   rr_pos(nb, up, nb - 1 - q2), e);
+                    v[4 + h] = issue_u<kLocal>(rU, uoff + q1, e);
+                    v[6 + h] = issue_u<kLocal>(rU, uoff + q2, e);
+                }
 #pragma unroll
-            for (int jj = 0; jj < kCg; ++jj) {
-                commit_tiled(L.Tj[jj], vTj[jj]);
-                commit_u(L.Uj[jj], L.Ujf[jj], vUj[jj]);
-                commit_tile(L.Vb[jj], vVb[jj]);
+                for (int h = 0; h < 2; ++h) {
+                    const int e = e0 + 256 * h;
+                    commit_tiled(L.T1, v[h], e);
+                    commit_tiled(L.T2, v[2 + h], e);
+                    commit_u(L.U1, nullptr, v[4 + h], e);
+                    commit_u(L.U2, nullptr, v[6 + h], e);
+                }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < kCg; ++jj) {
+                    // (a second copy of column pair 0 when there is no second)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        vRT[jj][h] = issue_tiled<kLocal>(rH, Mp, hb + I, hb + J, Kc[jj], Lc[jj], e0 + 256 * h);
+                        vRU[jj][h] = issue_u<kLocal>(rU, uoff + g + (jj < ncg ? jj : 0) * Q, e0 + 256 * h);
+                    }
+                    vRV[jj] = issue_tile<kLocal>(rV, Mp, I, J, Kc[jj], Lc[jj], e0);
+                }
             }
         }
         if (tid == 0) L.pub = 0;
-        __syncthreads();
+        if (t == 0) __syncthreads();
+        else lds_barrier();
         PROF(0);
 
-        // ---- B: D (waves 0-3), the first column pair's R (waves 4-7) -----------
-        {
+        // ---- B: D (waves 0-3); the R and V operands reach LDS (waves 4-7) ------
+        if (t > 0) {
             const int ti = (wave >> 1) & 1, tj = wave & 1;
             if (wave < 4) {
-                if (t > 0) {
-                    // Columns of block I from (T1, U1), of block J from (T2, U2).
-                    const double *Ta = tj == 0 ? L.T1 : L.T2;
-                    const double *Ua = (tj == 0 ? L.U1 : L.U2) + 16 * (tj == 0 ? o1 : o2);
-                    const f64x4 dacc = tile16d(Ta + 16 * ti * kLdd, kLdd, false, Ua, kLdd);
+                // Columns of block I from (T1, U1), of block J from (T2, U2).
+                const double *Ta = tj == 0 ? L.T1 : L.T2;
+                const double *Ua = (tj == 0 ? L.U1 : L.U2) + 16 * (tj == 0 ? o1 : o2);
+                const f64x4 dacc = tile16d(Ta + 16 * ti * kLdd, kLdd, false, Ua, kLdd);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) L.D[(16 * ti + orow + r) * kLd + 16 * tj + ocol] = (float)dacc[r];
+                for (int r = 0; r < 4; ++r) L.D[(16 * ti + orow + r) * kLd + 16 * tj + ocol] = (float)dacc[r];
+            } else {
+                const int e0 = tid & 255;
+#pragma unroll
+                for (int jj = 0; jj < kCg; ++jj) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        commit_tiled(L.Tj[jj], vRT[jj][h], e0 + 256 * h);
+                        commit_u(L.Uj[jj], L.Ujf[jj], vRU[jj][h], e0 + 256 * h);
+                    }
+                    commit_tile(L.Vb[jj], vRV[jj], e0);
                 }
-            } else if (t > 0) {
-                r_tile(L, 0, ti, tj);
             }
         }
         __syncthreads();
@@ -849,19 +880,17 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
             if (lane == 0) L.prof_w[wave] = now_ticks() - tC;
 #endif
         } else {
-            // Tasks: 0-3 the second column pair's R tiles (with their sums),
-            // 4-7 the sums of the first pair's R tiles, 8-15 V tiles.
+            // Tasks: 0-7 the R tiles of the column pairs (with their sums),
+            // 8-15 V tiles.
             for (int task = wave - 3; task < 16; task += 5) {
-                if (task < 4) {
-                    if (ncg > 1) {
-                        if (t > 0) r_tile(L, 1, task >> 1, task & 1);
-                        r_sums(L, 1, task >> 1, task & 1, I, J, Kc[1], Lc[1]);
-                    }
-                } else if (task < 8) {
-                    r_sums(L, 0, (task >> 1) & 1, task & 1, I, J, Kc[0], Lc[0]);
+                const int jj = (task >> 2) & 1;
+                const int K = jj ? Kc[1] : Kc[0], Lb = jj ? Lc[1] : Lc[0];   // (selects, not an indexed array)
+                if (jj >= ncg) continue;
+                if (task < 8) {
+                    if (t > 0) r_tile(L, jj, (task >> 1) & 1, task & 1);
+                    r_sums(L, jj, (task >> 1) & 1, task & 1, I, J, K, Lb);
                 } else {
-                    const int vt = task - 8, jj = vt >> 2;
-                    if (jj < ncg) v_task(L, A.V, Mp, jj, (vt >> 1) & 1, vt & 1, t == 0, I, J, Kc[jj], Lc[jj]);
+                    v_task(L, A.V, Mp, jj, (task >> 1) & 1, task & 1, t == 0, I, J, K, Lb);
                 }
             }
 #ifdef BJ_PROFILE
@@ -918,6 +947,9 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
         if (failed || bad) break;
 
         // ---- stop rule at the start of a sweep -------------------------------------
+        // (Checked per sweep, not per outer step: the quadratic convergence of
+        // the last sweep takes off(A) well below the tolerance, which the
+        // eigenvector accuracy needs on spectra with small gaps.)
         if (u == 0) {
             double so = 0.0, st = 0.0;
             long long cnt = 0;
