@@ -441,36 +441,69 @@ __device__ __forceinline__ void lds_barrier()
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 
-template <typename T, int MODE, int S>
-__global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
+// LDS of the chunk kernel: one set per (element type, mode), shared by the
+// slot-count variants that one persistent launch inlines. The three ring
+// slots are separate LDS arrays, which lets the compiler see that reading
+// one slot does not wait on the copies into the others.
+template <typename T, int MODE>
+struct DmaLds {
+    static constexpr int kPitch = (MODE == MODE_F32 && sizeof(T) == 4) ? 288 : 256;
+    static constexpr int kRawElems = KT * kPitch;
+    template <int K>
+    __device__ static __forceinline__ T *ring()
+    {
+        __shared__ __attribute__((aligned(16))) T r[kRawElems];
+        return r;
+    }
+    __device__ static __forceinline__ __bf16 *tiles()
+    {
+        __shared__ __attribute__((aligned(16))) __bf16 h[MODE == MODE_F32 ? 8 : 2 * 256 * kBfPitch];
+        return h;
+    }
+    __device__ static __forceinline__ float *shift()
+    {
+        __shared__ float v[256];
+        return v;
+    }
+};
+
+// Chunk c of a cube. CW is the width of one copy: 16 bytes (rows of whole
+// 16-byte pieces), or 4 bytes a lane for float32 rows of any band count and
+// alignment (a copy then moves 64 consecutive bands of one pixel, and a row
+// takes one to four copies). kSkip: a wave that holds no block skips the
+// products (narrow cubes of a batch). The stage walk starts at stage
+// c nst / spread.
+template <typename T, int MODE, int S, int CW, bool kSkip>
+__device__ __forceinline__ void cov_dma_body(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
     float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
-    const float *__restrict__ srow)
+    const float *__restrict__ srow, int64_t c, int64_t spread)
 {
     // Staged pixel rows of 256 elements (288 floats for the float32 products
     // of a float32 cube, whose two half-waves read rows one apart). A copy
     // instruction moves 16 bytes per lane: one float32 row (4 bands a lane),
     // or two uint16 rows (8 bands a lane, lanes 32-63 on the second pixel).
+    static_assert(CW == 16 || (CW == 4 && sizeof(T) == 4), "4-byte copies stage float32 rows");
     constexpr bool kU16 = sizeof(T) == 2;
     constexpr int pitch = (MODE == MODE_F32 && !kU16) ? 288 : 256;
-    constexpr int kPerLane = 16 / (int)sizeof(T);            // bands per lane and copy
+    constexpr int kPerLane = CW / (int)sizeof(T);            // bands per lane and copy
     constexpr int kRowsPerCopy = kU16 ? 2 : 1;
-    constexpr int kCopies = kDmaPix / kRowsPerCopy;          // copies per wave per stage
+    constexpr int kCopies = kDmaPix / kRowsPerCopy;          // 16-byte copies per wave per stage
     constexpr int kRawElems = KT * pitch;
     constexpr int kHalf = 256 * kBfPitch;   // bf16 per tile (hi, then lo)
     constexpr int kRawWords = (kRawElems * (int)sizeof(T) + 3) / 4;
-    __shared__ __attribute__((aligned(16))) T raw0[kRawElems];
-    __shared__ __attribute__((aligned(16))) T raw1[kRawElems];
-    __shared__ __attribute__((aligned(16))) T raw2[kRawElems];
-    __shared__ __attribute__((aligned(16))) __bf16 hl[MODE == MODE_F32 ? 8 : 2 * kHalf];
-    __shared__ float shv[256];
+    T *const raw0 = DmaLds<T, MODE>::template ring<0>();
+    T *const raw1 = DmaLds<T, MODE>::template ring<1>();
+    T *const raw2 = DmaLds<T, MODE>::template ring<2>();
+    __bf16 *const hl = DmaLds<T, MODE>::tiles();
+    float *const shv = DmaLds<T, MODE>::shift();
+    static_assert(kRawElems == DmaLds<T, MODE>::kRawElems, "ring slot size");
     static_assert(kRawWords * 4 >= kDmaWaves * 256 * (int)sizeof(double), "band-sum scratch");
     double(*red)[256] = reinterpret_cast<double(*)[256]>(static_cast<void *>(raw0));   // after the ring drains
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t c = blockIdx.x;
     const int64_t pbeg = c * chunk;
     const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
     const int64_t nst = (pend - pbeg + KT - 1) / KT;
@@ -482,12 +515,34 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     // spread over the chunk, wrapping around): chunks are equal power-of-two
     // multiples of bytes apart, and in lockstep every workgroup would hit
     // the same HBM channel at the same moment.
-    const int64_t rot = (c * nst) / gridDim.x;
+    const int64_t rot = (c * nst) / spread;
+    const int nq = (mpad + 63) >> 6;   // 4-byte copies per row
     // Copies of the stage at position t of this walk (pixels pbeg + 32 t'
     // with t' = (t + rot) mod nst; positions past the end copy the first
     // pixel) into ring slot R.
     auto issue = [&](T *R, int64_t t) {
         const int64_t tt = t < nst ? (t + rot < nst ? t + rot : t + rot - nst) : nst;
+        if constexpr (CW == 4) {
+#pragma unroll
+            for (int i = 0; i < kDmaPix; ++i) {
+                const int r = kDmaPix * wave + i;
+                const int64_t p = pbeg + tt * KT + r;
+                const bool pok = p < pend;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q < nq) {
+                        // Rows past the chunk end copy the shift row itself
+                        // and lanes past the last band its first element, so
+                        // both centre to zero.
+                        const int b = 64 * q + lane;
+                        const T *src = b < m ? (pok ? Y + p * ld : row0) + b : row0;
+                        __builtin_amdgcn_global_load_lds(static_cast<const void *>(src),
+                                                         static_cast<void *>(R + r * pitch + 64 * q), 4, 0, 0);
+                    }
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < kCopies; ++i) {
             const int r = kDmaPix * wave + kRowsPerCopy * i;           // first staged row of this copy
@@ -590,9 +645,10 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
             for (int kk = 0; kk < KT / 2; ++kk) {
                 const T *tr = R + (2 * kk + (lane >> 5)) * pitch;
 #pragma unroll
-                for (int e = 0; e < S; ++e)
+                for (int e = 0; e < S; ++e) {
                     acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(load_elem(tr + offI[e]) - shI[e],
                                                                  load_elem(tr + offJ[e]) - shJ[e], acc[e], 0, 0, 0);
+                }
             }
         } else {
 #pragma unroll
@@ -622,12 +678,21 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
     // first pixel, which centre to exact zeros and add nothing, so every step
     // is the same straight-line code with one copy wait.
     auto step = [&](T *cur, T *nxt, int64_t st) {
-        __builtin_amdgcn_s_waitcnt(waitcnt_vm(kCopies));
+        if constexpr (CW == 4) {
+            switch (nq) {   // the copies of the stage after this one may still be in flight
+            case 1: __builtin_amdgcn_s_waitcnt(waitcnt_vm(kDmaPix)); break;
+            case 2: __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * kDmaPix)); break;
+            case 3: __builtin_amdgcn_s_waitcnt(waitcnt_vm(3 * kDmaPix)); break;
+            default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(4 * kDmaPix)); break;
+            }
+        } else {
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(kCopies));
+        }
         lds_barrier();
         issue(nxt, st + 2);
         centre(cur);
         if constexpr (MODE != MODE_F32) lds_barrier();
-        products(cur);
+        if (!kSkip || nbl > wave) products(cur);
         if constexpr (kTwoLevel) {
             if ((st + 1) % kFlush == 0) {
 #pragma unroll
@@ -669,6 +734,28 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
         partSum[c * mpad + b] = t;
         partShift[c * mpad + b] = shv[b];
     }
+}
+
+template <typename T, int MODE, int S>
+__global__ __launch_bounds__(kDmaThreads) void cov_partial_dma_kernel(
+    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
+    const float *__restrict__ srow)
+{
+    cov_dma_body<T, MODE, S, 16, false>(Y, n, m, ld, chunk, nb, nblk, mpad, partS, partSum, partShift, srow,
+                                        (int64_t)blockIdx.x, (int64_t)gridDim.x);
+}
+
+// Float32 cubes whose rows are not whole 16-byte pieces (any band count, any
+// row pitch): the same kernel with 4-byte copies.
+template <int MODE, int S>
+__global__ __launch_bounds__(kDmaThreads) void cov_partial_dma4_kernel(
+    const float *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad,
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
+    const float *__restrict__ srow)
+{
+    cov_dma_body<float, MODE, S, 4, false>(Y, n, m, ld, chunk, nb, nblk, mpad, partS, partSum, partShift, srow,
+                                           (int64_t)blockIdx.x, (int64_t)gridDim.x);
 }
 
 // ---- band-sequential cubes: Y[b * ld + p] --------------------------------
@@ -1206,6 +1293,35 @@ __global__ __launch_bounds__(kThreads) void cov_partial_batched_kernel(char *ws,
     }
 }
 
+// Float32 cubes of the batch: the same queue over the 4-byte-copy chunk
+// kernel, with the slot count of each item's cube.
+template <int MODE>
+__global__ __launch_bounds__(kDmaThreads) void cov_partial_batched_dma_kernel(char *ws, int nc, int64_t total)
+{
+    __shared__ int64_t item_sh;
+    BatchHeader *h = reinterpret_cast<BatchHeader *>(ws);
+    const BatchCube *t = batch_table(ws);
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&h->counter[0], 1u);
+        __syncthreads();
+        const int64_t item = item_sh;
+        if (item >= total) break;
+        const BatchCube &cb = t[batch_find<&BatchCube::w_cov>(t, nc, item)];
+#define PCA_BATCH_BODY(S)                                                                                          \
+    cov_dma_body<float, MODE, S, 4, true>(static_cast<const float *>(cb.Y), cb.n, cb.m, cb.ld, cb.cov.chunk, cb.cov.nb, \
+                                          cb.cov.nblk, cb.cov.mpad, cb.partS, cb.partSum, cb.partShift, cb.srow,       \
+                                          item - cb.w_cov, cb.cov.nchunks)
+        switch (dma_slots(cb.cov.nb)) {
+        case 2: PCA_BATCH_BODY(2); break;
+        case 3: PCA_BATCH_BODY(3); break;
+        case 4: PCA_BATCH_BODY(4); break;
+        default: PCA_BATCH_BODY(5); break;
+        }
+#undef PCA_BATCH_BODY
+    }
+}
+
 __global__ __launch_bounds__(1024) void cov_finalize_part_batched_kernel(const char *ws, int nc)
 {
     const BatchCube *t = batch_table(ws);
@@ -1275,6 +1391,24 @@ hipError_t launch_dma_m(const T *Y, int64_t n, int m, int64_t ld, const CovPlan 
                            p.mpad, partS, partSum, partShift, srow);
         break;
     }
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_dma4_m(const float *Y, int64_t n, int m, int64_t ld, const CovPlan &p, float *partS,
+                         double *partSum, float *partShift, const float *srow, hipStream_t st)
+{
+    const dim3 grid((unsigned)p.nchunks), block(kDmaThreads);
+#define PCA_DMA4(S)                                                                                                \
+    hipLaunchKernelGGL((cov_partial_dma4_kernel<MODE, S>), grid, block, 0, st, Y, n, m, ld, p.chunk, p.nb, p.nblk, \
+                       p.mpad, partS, partSum, partShift, srow)
+    switch (dma_slots(p.nb)) {
+    case 2: PCA_DMA4(2); break;
+    case 3: PCA_DMA4(3); break;
+    case 4: PCA_DMA4(4); break;
+    default: PCA_DMA4(5); break;
+    }
+#undef PCA_DMA4
     return hipGetLastError();
 }
 
@@ -1422,12 +1556,15 @@ hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t l
         return launch_partial_dma(static_cast<const uint16_t *>(Y), n, m, ld, mode, plan, partS, partSum, partShift,
                                   srow, st);
     }
-    const bool v4 = vec4_ok(Y, dt, m, ld);
     if (dt == PCA_IN_F32) {
         const float *y = static_cast<const float *>(Y);
-        return v4 ? launch_partial_t<float, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, srow, st)
-                  : launch_partial_t<float, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, srow, st);
+        switch (mode) {
+        case MODE_F32: return launch_dma4_m<MODE_F32>(y, n, m, ld, plan, partS, partSum, partShift, srow, st);
+        case MODE_BF16X3: return launch_dma4_m<MODE_BF16X3>(y, n, m, ld, plan, partS, partSum, partShift, srow, st);
+        default: return launch_dma4_m<MODE_BF16X4>(y, n, m, ld, plan, partS, partSum, partShift, srow, st);
+        }
     }
+    const bool v4 = vec4_ok(Y, dt, m, ld);
     const uint16_t *y = static_cast<const uint16_t *>(Y);
     return v4 ? launch_partial_t<uint16_t, 4>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, srow, st)
               : launch_partial_t<uint16_t, 1>(y, n, m, ld, centered, mode, plan, partS, partSum, partShift, srow, st);
@@ -1451,26 +1588,30 @@ hipError_t launch_cov_batched(int dt, int mode, const char *ws, const int64_t to
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    int64_t g = (int64_t)cus * 2;
+    // Register-staged uint16 kernel: two workgroups a CU; float32 copy
+    // kernel: one (its stage ring fills most of the LDS).
+    int64_t g = (int64_t)cus * (dt == PCA_IN_F32 ? 1 : 2);
     if (g > total[0]) g = total[0];
     if (g < 1) g = 1;
     char *w = const_cast<char *>(ws);
-    const dim3 grid((unsigned)g), block(kThreads);
+    const dim3 grid((unsigned)g), block(kThreads), dgrid((unsigned)g), dblock(kDmaThreads);
     const dim3 sgrid(8u, (unsigned)n_cubes);
     if (dt == PCA_IN_F32) hipLaunchKernelGGL(cov_shift_batched_kernel<float>, sgrid, dim3(kShiftThreads), 0, st, ws);
     else hipLaunchKernelGGL(cov_shift_batched_kernel<uint16_t>, sgrid, dim3(kShiftThreads), 0, st, ws);
 #define PCA_COV_B(T, M)                                                                                           \
     hipLaunchKernelGGL((cov_partial_batched_kernel<T, M>), grid, block, 0, st, w, n_cubes, total[0])
+#define PCA_COV_BD(M) hipLaunchKernelGGL((cov_partial_batched_dma_kernel<M>), dgrid, dblock, 0, st, w, n_cubes, total[0])
     if (dt == PCA_IN_F32) {
-        if (mode == MODE_F32) PCA_COV_B(float, MODE_F32);
-        else if (mode == MODE_BF16X3) PCA_COV_B(float, MODE_BF16X3);
-        else PCA_COV_B(float, MODE_BF16X4);
+        if (mode == MODE_F32) PCA_COV_BD(MODE_F32);
+        else if (mode == MODE_BF16X3) PCA_COV_BD(MODE_BF16X3);
+        else PCA_COV_BD(MODE_BF16X4);
     } else {
         if (mode == MODE_F32) PCA_COV_B(uint16_t, MODE_F32);
         else if (mode == MODE_BF16X3) PCA_COV_B(uint16_t, MODE_BF16X3);
         else PCA_COV_B(uint16_t, MODE_BF16X4);
     }
 #undef PCA_COV_B
+#undef PCA_COV_BD
     hipLaunchKernelGGL(cov_finalize_part_batched_kernel, dim3((unsigned)total[1]), dim3(1024), 0, st, ws, n_cubes);
     hipLaunchKernelGGL(cov_finalize_sum_batched_kernel, dim3((unsigned)total[2]), dim3(1024), 0, st, ws, n_cubes);
     return hipGetLastError();
