@@ -47,6 +47,10 @@ MFMA_F32_PEAK_TFS = 157.3      # dense FP32 matrix
 FP32_VECTOR_PEAK_TFS = 157.3   # FP32 vector (packed FMA counted), 256 CUs at 2.4 GHz
 MFMA_BF16_PEAK_TFS = 2500.0    # dense BF16 matrix
 EIG_TOL = 1e-5
+# Covariance forms timed on the headline cube; the headline is the fastest of
+# the metric's forms (float32 and split-bfloat16) within EIG_TOL.
+DEFAULT_MODES = "f32,bf16x3,bf16x4,fp16x3"
+HEADLINE_MODES = ("f32", "bf16x3", "bf16x4")
 JACOBI_BLOCK_MIN_BANDS = 96    # the library's default form: block-cyclic from this band count
 
 
@@ -259,7 +263,7 @@ def run_batch(P, synth, torch, steps, warmup, mode="f32", lanes=1, autotune=Fals
 
 
 def bench_batch(P, synth, torch, args):
-    mode = args.modes.split(",")[0] if args.modes != "f32,bf16x3,bf16x4" else "f32"
+    mode = args.modes.split(",")[0] if args.modes != DEFAULT_MODES else "f32"
     rec = run_batch(P, synth, torch, args.steps, args.warmup, mode, args.lanes, args.autotune,
                     0 if args.no_accuracy else 8)
     out = dict(metric=METRIC, value=rec["value"], unit="Mpixel·band/s", n_gpus=1, steps=args.steps,
@@ -387,7 +391,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="f32,bf16x3,bf16x4")
+    ap.add_argument("--modes", default=DEFAULT_MODES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="cube224: skip the batch64 and grad sub-records")
@@ -462,8 +466,11 @@ def main(argv=None):
         modes[mode] = rec
         log(mode, json.dumps(rec))
 
-    ok = [mm for mm, r in modes.items() if r.get("eig_err", 0.0) <= EIG_TOL]
-    best = min(ok or list(modes), key=lambda mm: modes[mm]["ms_per_step"])
+    # The headline is the metric's comparison (split-bfloat16 against
+    # float32); the float16 split is measured and reported beside them.
+    cand = [mm for mm in modes if mm in HEADLINE_MODES] or list(modes)
+    ok = [mm for mm in cand if modes[mm].get("eig_err", 0.0) <= EIG_TOL]
+    best = min(ok or cand, key=lambda mm: modes[mm]["ms_per_step"])
     br = modes[best]
 
     # Rooflines. End to end: the algorithmic bytes of the method (the cube
@@ -503,7 +510,7 @@ def main(argv=None):
 
     out = dict(metric=METRIC, value=br["value"], unit="Mpixel·band/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=br["ms_per_step"], higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype={"f32": "f32", "bf16x3": "bf16", "bf16x4": "bf16"}[best], data="synthetic",
+               vs_baseline=None, dtype={"f32": "f32", "bf16x3": "bf16", "bf16x4": "bf16", "fp16x3": "f16"}[best], data="synthetic",
                config=dict(workload="224-band radiance cube, 1024x1024 px (uint16 counts -> float32), k=10",
                            n_pixels=n, n_bands=m, k=k, cov_mode=best),
                roofline=roof, e2e_roofline=e2e, kernels=kern, modes=modes)

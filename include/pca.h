@@ -66,8 +66,20 @@ typedef enum {
     PCA_COV_BF16X3 = 1,       /* split x = hi + lo into two bfloat16 terms;
                                  hi*hi + hi*lo + lo*hi with bfloat16 MFMA and
                                  float32 accumulation (lo*lo dropped) */
-    PCA_COV_BF16X4 = 2        /* as BF16X3 plus lo*lo: the exact product of
+    PCA_COV_BF16X4 = 2,       /* as BF16X3 plus lo*lo: the exact product of
                                  the 16-significant-bit split */
+    PCA_COV_FP16X3 = 3        /* split x sc = hi + lo into two float16 terms
+                                 (sc: a per-band power of two that the
+                                 covariance call derives from a pixel sample:
+                                 1/2 for uint16 cubes, the largest sampled
+                                 |x| brought to at most 16 for float32 cubes);
+                                 hi*hi + hi*lo + lo*hi with float16 MFMA and
+                                 float32 accumulation, results scaled back by
+                                 1/(sc_i sc_j). About 22 significant bits per
+                                 value; a float32 value more than 2^12 times
+                                 the largest sampled deviation of its band
+                                 overflows float16 and makes the covariance
+                                 non-finite */
 } pca_cov_mode;
 
 /* Operation selector for pca_workspace_size. */

@@ -9,6 +9,7 @@ from ._lib import (  # noqa: F401
     LIB_PATH,
     PCA_COV_BF16X3,
     PCA_COV_BF16X4,
+    PCA_COV_FP16X3,
     PCA_COV_F32,
     PCA_IN_F32,
     PCA_IN_U16,

@@ -19,12 +19,12 @@ LIB_PATH = os.path.join(_PKG, "libpca.so")
 
 PCA_OK, PCA_ERR_ARG, PCA_ERR_UNSUPPORTED, PCA_ERR_WORKSPACE, PCA_ERR_HIP = range(5)
 PCA_IN_F32, PCA_IN_U16, PCA_IN_F32_BSQ, PCA_IN_U16_BSQ = 0, 1, 2, 3
-PCA_COV_F32, PCA_COV_BF16X3, PCA_COV_BF16X4 = 0, 1, 2
+PCA_COV_F32, PCA_COV_BF16X3, PCA_COV_BF16X4, PCA_COV_FP16X3 = 0, 1, 2, 3
 PCA_JACOBI_FP64_ANGLES, PCA_JACOBI_OVERLAP_REPLAY, PCA_JACOBI_ONE_CU, PCA_JACOBI_BLOCK = 1, 2, 4, 8
 JACOBI_FORMS = {"auto": 0, "one_cu": PCA_JACOBI_ONE_CU, "block": PCA_JACOBI_BLOCK}
 PCA_OP_CENTER, PCA_OP_COVARIANCE, PCA_OP_JACOBI, PCA_OP_PROJECT, PCA_OP_BACKWARD = range(5)
 
-COV_MODES = {"f32": PCA_COV_F32, "bf16x3": PCA_COV_BF16X3, "bf16x4": PCA_COV_BF16X4}
+COV_MODES = {"f32": PCA_COV_F32, "bf16x3": PCA_COV_BF16X3, "bf16x4": PCA_COV_BF16X4, "fp16x3": PCA_COV_FP16X3}
 
 # pca_info: int32 sweeps, converged, nonfinite, floor_hit; double off_rel;
 # int64 rotations; int32 steps, n_bands.

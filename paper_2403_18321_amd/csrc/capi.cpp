@@ -129,7 +129,7 @@ pca_status pca_workspace_size(int op, int64_t n_pixels, int32_t n_bands, int32_t
         *bytes = center_ws(pca::cov_plan(n_pixels, n_bands), n_bands);
         return PCA_OK;
     case PCA_OP_COVARIANCE:
-        if (n_pixels < 2 || mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
+        if (n_pixels < 2 || mode < PCA_COV_F32 || mode > PCA_COV_FP16X3) return PCA_ERR_ARG;
         *bytes = cov_ws(pca::cov_plan(n_pixels, n_bands));
         return PCA_OK;
     case PCA_OP_JACOBI:
@@ -171,7 +171,7 @@ pca_status pca_covariance(const void *Y, int dt, int64_t n_pixels, int32_t n_ban
     pca_status s = check_cube(Y, dt, n_pixels, n_bands, ld_y);
     if (s != PCA_OK) return s;
     if (!C || !ws || !aligned(ws, kWsAlign) || !aligned(C, 4) || (mean && !aligned(mean, 4))) return PCA_ERR_ARG;
-    if (mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
+    if (mode < PCA_COV_F32 || mode > PCA_COV_FP16X3) return PCA_ERR_ARG;
     if (input_is_centered != 0 && input_is_centered != 1) return PCA_ERR_ARG;
     const pca::CovPlan plan = pca::cov_plan(n_pixels, n_bands);
     if (ws_bytes < cov_ws(plan)) return PCA_ERR_WORKSPACE;
@@ -274,7 +274,7 @@ pca_status pca_backward(const float *Y, int64_t n_pixels, int32_t n_bands, int64
 pca_status pca_batched_workspace_size(const pca_cube *cubes, int32_t n_cubes, int mode, int32_t max_sweeps,
                                       const pca_batch_tuning *tuning, size_t *bytes)
 {
-    if (!bytes || mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
+    if (!bytes || mode < PCA_COV_F32 || mode > PCA_COV_FP16X3) return PCA_ERR_ARG;
     int64_t total[6];
     // The element type does not change the sizes; check the cube pointers at
     // the weaker (uint16) alignment here, pca_batched checks them again.
@@ -287,7 +287,7 @@ pca_status pca_batched(const pca_cube *cubes, const pca_cube *cubes_dev, int32_t
 {
     if (is_bsq(dt)) return PCA_ERR_UNSUPPORTED;   // the batched form takes BIP cubes
     if (!cubes_dev || !aligned(cubes_dev, 8) || !ws || !aligned(ws, kWsAlign) || !valid_dt(dt)) return PCA_ERR_ARG;
-    if (mode < PCA_COV_F32 || mode > PCA_COV_BF16X4) return PCA_ERR_ARG;
+    if (mode < PCA_COV_F32 || mode > PCA_COV_FP16X3) return PCA_ERR_ARG;
     if (!(tol >= 0.0) || !isfinite(tol) || (fp64_angles != 0 && fp64_angles != 1)) return PCA_ERR_ARG;
     size_t need = 0;
     int64_t total[6];

@@ -39,7 +39,7 @@ constexpr int kMaxSlots = 9;    // accumulator blocks per wave at 8 blocks per s
 constexpr int kFlush = 8;       // stages per first-level MFMA accumulation (float32 mode)
 constexpr int kBfPitch = KT + 8;  // bf16 per band row in LDS (80 bytes)
 
-enum { MODE_F32 = 0, MODE_BF16X3 = 1, MODE_BF16X4 = 2 };
+enum { MODE_F32 = 0, MODE_BF16X3 = 1, MODE_BF16X4 = 2, MODE_FP16X3 = 3 };
 
 // Pixel-major float32 stage pitch (floats): pitch % 64 == 32 so the two
 // half-waves of an MFMA operand read fall on disjoint LDS banks.
@@ -65,10 +65,82 @@ __host__ __device__ inline int cov_slots(int nb)
 // Compact id for nb blocks per side (the layout of the partial results).
 __device__ inline int compact_block(int bi, int bj, int nb) { return bi * nb - bi * (bi - 1) / 2 + (bj - bi); }
 
-__device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+
+// The split forms. bfloat16: x = hi + lo (+ a remainder below 2^-16 |x|).
+// float16 (MODE_FP16X3): x sc = hi + lo, sc the band's power-of-two scale
+// (a float16 keeps 11 significant bits but only exponents -14..15, so each
+// band is scaled into that range first; the pair then holds about 22 bits).
+// Both store 16-bit patterns in the same tiles (bfloat16 storage type).
+template <int MODE>
+__device__ __forceinline__ void split2(f32x2 v, float sc, bf16x2 &h, bf16x2 &l)
 {
-    hi = (__bf16)x;
-    lo = (__bf16)(x - (float)hi);
+    if constexpr (MODE == MODE_FP16X3) {
+        const f32x2 t = {v[0] * sc, v[1] * sc};
+        const f16x2 hh = __builtin_convertvector(t, f16x2);
+        const f32x2 r = t - __builtin_convertvector(hh, f32x2);
+        const f16x2 ll = __builtin_convertvector(r, f16x2);
+        h = __builtin_bit_cast(bf16x2, hh);
+        l = __builtin_bit_cast(bf16x2, ll);
+    } else {
+        h = __builtin_convertvector(v, bf16x2);
+        const f32x2 r = v - __builtin_convertvector(h, f32x2);
+        l = __builtin_convertvector(r, bf16x2);
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void split1(float x, float sc, __bf16 &hi, __bf16 &lo)
+{
+    if constexpr (MODE == MODE_FP16X3) {
+        const float t = x * sc;
+        const _Float16 hh = (_Float16)t;
+        hi = __builtin_bit_cast(__bf16, hh);
+        lo = __builtin_bit_cast(__bf16, (_Float16)(t - (float)hh));
+    } else {
+        hi = (__bf16)x;
+        lo = (__bf16)(x - (float)hi);
+    }
+}
+
+// hi_i hi_j + hi_i lo_j + lo_i hi_j (+ lo_i lo_j for bf16x4) added to a.
+template <int MODE>
+__device__ __forceinline__ f32x16 split_products(bf16x8 hi_i, bf16x8 lo_i, bf16x8 hi_j, bf16x8 lo_j, f32x16 a)
+{
+    if constexpr (MODE == MODE_FP16X3) {
+        const f16x8 hi = __builtin_bit_cast(f16x8, hi_i), li = __builtin_bit_cast(f16x8, lo_i);
+        const f16x8 hj = __builtin_bit_cast(f16x8, hi_j), lj = __builtin_bit_cast(f16x8, lo_j);
+        a = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi, hj, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi, lj, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_32x32x16_f16(li, hj, a, 0, 0, 0);
+    } else {
+        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
+        if constexpr (MODE == MODE_BF16X4) a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
+    }
+    return a;
+}
+
+// Per-band scales of the float16 split in the shift buffer: sc at srow + 512,
+// 1 / sc at srow + 768 (powers of two, so both are exact).
+constexpr int kScaleRow = 512, kInvScaleRow = 768;
+
+// Entry r of a lane's 32x32 block (bi, bj) product in the scale of the data
+// (the float16 split's sums carry the factor sc_i sc_j).
+template <int MODE>
+__device__ __forceinline__ float unscaled(float v, const float *__restrict__ srow, int bi, int bj, int r, int lane)
+{
+    if constexpr (MODE == MODE_FP16X3) {
+        const int i = 32 * bi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);   // MFMA 32x32 result layout
+        const int j = 32 * bj + (lane & 31);
+        return v * srow[kInvScaleRow + i] * srow[kInvScaleRow + j];
+    } else {
+        return v;
+    }
 }
 
 // ---- pass 0: the shift row ------------------------------------------------
@@ -88,8 +160,14 @@ __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 // cubes round it to 8 significant bits (a bfloat16 value), which keeps it
 // within 2^-9 of the sample mean and makes it an integer from 128 on, so that
 // integer-valued cubes (converted sensor counts) stay integer-valued after
-// the shift and their bfloat16 hi/lo split stays exact up to 2^16. Shift
-// area: float32 s[256], then the cube-type row [256].
+// the shift and their bfloat16 hi/lo split stays exact up to 2^16.
+// The same pass sets the per-band power-of-two scales of the float16 split:
+// 1/2 for uint16 cubes (|y - s| < 2^16, so y - s scaled by 1/2 is below the
+// float16 maximum and its 17 significant bits fit the hi/lo pair exactly);
+// for float32 cubes the largest sampled |y - s| is scaled to at most 2^4,
+// which leaves a factor 2^12 for values beyond the sample before a float16
+// overflows (an overflow makes the covariance non-finite, reported as such).
+// Shift area: float32 s[256], the cube-type row [256], sc[256], 1/sc[256].
 constexpr int kShiftRuns = 8;
 constexpr int kShiftSample = 32 * kShiftRuns;   // 256 pixels
 constexpr int kShiftThreads = 256;              // one 32-band block a workgroup
@@ -109,6 +187,7 @@ __device__ __forceinline__ void cov_shift_body(const T *__restrict__ Y, int64_t 
                                float *__restrict__ srow)
 {
     __shared__ double red[32][9];
+    __shared__ float svs[32], dev[32][9];
     const int tid = threadIdx.x;
     const bool all = n <= kShiftSample;
     const int ns = all ? (int)n : kShiftSample;
@@ -157,8 +236,34 @@ __device__ __forceinline__ void cov_shift_body(const T *__restrict__ Y, int64_t 
             else sv = (float)(__bf16)(float)mean;   // 8 significant bits (see above)
         }
         srow[bq] = sv;
+        svs[tid] = sv;
         if constexpr (sizeof(T) == 2) rowT[bq] = (T)(unsigned)sv;
         else rowT[bq] = sv;
+    }
+    __syncthreads();
+    // Largest sampled deviation from the shift, per band.
+    float dmax = 0.f;
+#pragma unroll
+    for (int j = 0; j < kShiftSample / 8; ++j)
+        if (bok && i0 + 8 * j < ns) dmax = fmaxf(dmax, fabsf(v[j] - svs[bl]));
+    dev[bl][i0] = dmax;
+    __syncthreads();
+    if (tid < 32) {
+        const int bq = 32 * bb + tid;
+        float mx = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mx = fmaxf(mx, dev[tid][q]);
+        int e = 0;
+        if constexpr (sizeof(T) == 2) {
+            e = -1;
+        } else if (bq < m && mx > 0.f && mx <= 3.0e38f) {
+            int k;
+            (void)frexpf(mx, &k);   // mx < 2^k
+            e = 4 - k;
+            e = e > 100 ? 100 : (e < -100 ? -100 : e);
+        }
+        srow[kScaleRow + bq] = ldexpf(1.f, e);
+        srow[kInvScaleRow + bq] = ldexpf(1.f, -e);
     }
 }
 
@@ -193,12 +298,13 @@ __device__ __forceinline__ void cov_partial_body(
     const int pf = f32_pitch(mpad);
 
     // Shift: the cube's shift row (zero when the cube is centred).
-    float shift[4];
+    float shift[4], scs[4];
     double sums[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int b = slot_band<VEC>(lane, s);
         shift[s] = (!centered && b < m) ? srow[b] : 0.f;
+        scs[s] = (MODE == MODE_FP16X3 && b < mpad) ? srow[kScaleRow + b] : 1.f;
         sums[s] = 0.0;
     }
 
@@ -278,7 +384,7 @@ __device__ __forceinline__ void cov_partial_body(
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         __bf16 hh, ll;
-                        split_bf16(x[i], hh, ll);
+                        split1<MODE>(x[i], scs[s], hh, ll);
                         h[i] = hh;
                         l[i] = ll;
                     }
@@ -324,13 +430,7 @@ __device__ __forceinline__ void cov_partial_body(
                     const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&loT[offI[e] + 16 * kk]);
                     const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hiT[offJ[e] + 16 * kk]);
                     const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&loT[offJ[e] + 16 * kk]);
-                    f32x16 a = acc[e];
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
-                    if constexpr (MODE == MODE_BF16X4)
-                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
-                    acc[e] = a;
+                    acc[e] = split_products<MODE>(hi_i, lo_i, hi_j, lo_j, acc[e]);
                 }
             }
         }
@@ -361,7 +461,9 @@ __device__ __forceinline__ void cov_partial_body(
             block_of_id(4 * e + wave, bi, bj);
             float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) dst[r * 64] = kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r];
+            for (int r = 0; r < 16; ++r)
+                dst[r * 64] = unscaled<MODE>(kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r], srow, bi, bj, r,
+                                             lane);
         }
     }
 
@@ -437,9 +539,6 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
 }
-
-typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
-typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 
 // LDS of the chunk kernel: one set per (element type, mode), shared by the
 // slot-count variants that one persistent launch inlines. The three ring
@@ -596,9 +695,12 @@ __device__ __forceinline__ void cov_dma_body(
     lds_barrier();   // shv visible
     // Centring works on bands lane + 64 s (consecutive lanes, consecutive
     // band rows of the tiles, so their tile stores spread over the banks).
-    float shb[4];
+    float shb[4], scb[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) shb[s] = shv[lane + 64 * s];
+    for (int s = 0; s < 4; ++s) {
+        shb[s] = shv[lane + 64 * s];
+        scb[s] = (MODE == MODE_FP16X3 && lane + 64 * s < mpad) ? srow[kScaleRow + lane + 64 * s] : 1.f;
+    }
     float shI[S], shJ[S];
     if constexpr (MODE == MODE_F32) {
 #pragma unroll
@@ -625,9 +727,8 @@ __device__ __forceinline__ void cov_dma_body(
 #pragma unroll
                 for (int q = 0; q < kDmaPix / 2; ++q) {
                     const f32x2 v = {x[2 * q], x[2 * q + 1]};
-                    const bf16x2 hh = __builtin_convertvector(v, bf16x2);
-                    const f32x2 r = v - __builtin_convertvector(hh, f32x2);
-                    const bf16x2 ll = __builtin_convertvector(r, bf16x2);
+                    bf16x2 hh, ll;
+                    split2<MODE>(v, scb[s], hh, ll);
                     h[2 * q] = hh[0];
                     h[2 * q + 1] = hh[1];
                     l[2 * q] = ll[0];
@@ -659,13 +760,7 @@ __device__ __forceinline__ void cov_dma_body(
                     const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
                     const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
                     const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
-                    f32x16 a = acc[e];
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
-                    if constexpr (MODE == MODE_BF16X4)
-                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
-                    acc[e] = a;
+                    acc[e] = split_products<MODE>(hi_i, lo_i, hi_j, lo_j, acc[e]);
                 }
             }
         }
@@ -721,7 +816,9 @@ __device__ __forceinline__ void cov_dma_body(
             block_of_id(kDmaWaves * e + wave, bi, bj);
             float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) dst[r * 64] = kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r];
+            for (int r = 0; r < 16; ++r)
+                dst[r * 64] = unscaled<MODE>(kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r], srow, bi, bj, r,
+                                             lane);
         }
     }
 #pragma unroll
@@ -796,12 +893,13 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
     const int64_t nst = (pend - pbeg + KT - 1) / KT;
 
     // Shift: the cube's shift row, per band.
-    float sh[8];
+    float sh[8], scj[8];
     double sums[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int b = bg + 32 * j;
         sh[j] = b < m ? srow[b] : 0.f;
+        scj[j] = (MODE == MODE_FP16X3 && b < mpad) ? srow[kScaleRow + b] : 1.f;
         sums[j] = 0.0;
     }
 
@@ -857,9 +955,8 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
                     *reinterpret_cast<f32x2 *>(&tileF[b * kBsqPitchF + 2 * pp]) = f32x2{x0, x1};
                 } else {
                     const f32x2 xv = {x0, x1};
-                    const bf16x2 hh = __builtin_convertvector(xv, bf16x2);
-                    const f32x2 r = xv - __builtin_convertvector(hh, f32x2);
-                    const bf16x2 ll = __builtin_convertvector(r, bf16x2);
+                    bf16x2 hh, ll;
+                    split2<MODE>(xv, scj[j], hh, ll);
                     *reinterpret_cast<bf16x2 *>(&hl[b * kBfPitch + 2 * pp]) = hh;
                     *reinterpret_cast<bf16x2 *>(&hl[kHalf + b * kBfPitch + 2 * pp]) = ll;
                 }
@@ -890,13 +987,7 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
                     const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
                     const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
                     const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
-                    f32x16 a = acc[e];
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
-                    if constexpr (MODE == MODE_BF16X4)
-                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
-                    acc[e] = a;
+                    acc[e] = split_products<MODE>(hi_i, lo_i, hi_j, lo_j, acc[e]);
                 }
             }
         }
@@ -921,7 +1012,9 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
             block_of_id(idbase + kDmaWaves * e + wave, bi, bj);
             float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) dst[r * 64] = kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r];
+            for (int r = 0; r < 16; ++r)
+                dst[r * 64] = unscaled<MODE>(kTwoLevel ? acc2[e % kSlots2][r] + acc[e][r] : acc[e][r], srow, bi, bj, r,
+                                             lane);
         }
     }
     // Band sums: the 16 threads of a band group (consecutive lanes) hold
@@ -984,12 +1077,13 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
         return pbeg + tt * KT;
     };
 
-    float sh[8];
+    float sh[8], scj[8];
     double sums[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int b = bg + 32 * j;
         sh[j] = b < m ? srow[b] : 0.f;
+        scj[j] = (MODE == MODE_FP16X3 && b < mpad) ? srow[kScaleRow + b] : 1.f;
         sums[j] = 0.0;
     }
     asm volatile("" ::: "memory");   // the shift loads stay ahead of the copies
@@ -1046,9 +1140,8 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
             const float x1 = (b < m && v1) ? r1 - sh[j] : 0.f;
             sums[j] += (double)(x0 + x1);
             const f32x2 xv = {x0, x1};
-            const bf16x2 hh = __builtin_convertvector(xv, bf16x2);
-            const f32x2 r = xv - __builtin_convertvector(hh, f32x2);
-            const bf16x2 ll = __builtin_convertvector(r, bf16x2);
+            bf16x2 hh, ll;
+            split2<MODE>(xv, scj[j], hh, ll);
             *reinterpret_cast<bf16x2 *>(&hl[b * kBfPitch + 2 * pp]) = hh;
             *reinterpret_cast<bf16x2 *>(&hl[kHalf + b * kBfPitch + 2 * pp]) = ll;
         }
@@ -1063,13 +1156,7 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
                 const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
                 const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
                 const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
-                f32x16 a = acc[e];
-                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, hi_j, a, 0, 0, 0);
-                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi_i, lo_j, a, 0, 0, 0);
-                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, hi_j, a, 0, 0, 0);
-                if constexpr (MODE == MODE_BF16X4)
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo_i, lo_j, a, 0, 0, 0);
-                acc[e] = a;
+                acc[e] = split_products<MODE>(hi_i, lo_i, hi_j, lo_j, acc[e]);
             }
         }
     };
@@ -1103,7 +1190,7 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
             block_of_id(kDmaWaves * e + wave, bi, bj);
             float *dst = partS + ((c * nblk + compact_block(bi, bj, nb)) * 16) * 64 + lane;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) dst[r * 64] = acc[e][r];
+            for (int r = 0; r < 16; ++r) dst[r * 64] = unscaled<MODE>(acc[e][r], srow, bi, bj, r, lane);
         }
     }
     // Band sums: the 16 threads of a band group (consecutive lanes) hold
@@ -1475,11 +1562,13 @@ hipError_t launch_partial_bsq(const T *Y, int64_t n, int m, int64_t ld, int mode
 {
     if (bsq_dma_ok(Y, (int)sizeof(T), mode, n, ld)) {
         if (mode == MODE_BF16X3) return launch_bsq_dma_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
+        if (mode == MODE_FP16X3) return launch_bsq_dma_m<T, MODE_FP16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
         return launch_bsq_dma_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     }
     switch (mode) {
     case MODE_F32: return launch_bsq_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     case MODE_BF16X3: return launch_bsq_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
+    case MODE_FP16X3: return launch_bsq_m<T, MODE_FP16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     default: return launch_bsq_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     }
 }
@@ -1491,6 +1580,7 @@ hipError_t launch_partial_dma(const T *Y, int64_t n, int m, int64_t ld, int mode
     switch (mode) {
     case MODE_F32: return launch_dma_m<T, MODE_F32>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     case MODE_BF16X3: return launch_dma_m<T, MODE_BF16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
+    case MODE_FP16X3: return launch_dma_m<T, MODE_FP16X3>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     default: return launch_dma_m<T, MODE_BF16X4>(Y, n, m, ld, p, partS, partSum, partShift, srow, st);
     }
 }
@@ -1512,6 +1602,8 @@ hipError_t launch_partial_t(const T *Y, int64_t n, int m, int64_t ld, int center
         return launch_partial_m<T, VEC, MODE_F32>(Y, n, m, ld, centered, p, partS, partSum, partShift, srow, st);
     case MODE_BF16X3:
         return launch_partial_m<T, VEC, MODE_BF16X3>(Y, n, m, ld, centered, p, partS, partSum, partShift, srow, st);
+    case MODE_FP16X3:
+        return launch_partial_m<T, VEC, MODE_FP16X3>(Y, n, m, ld, centered, p, partS, partSum, partShift, srow, st);
     default:
         return launch_partial_m<T, VEC, MODE_BF16X4>(Y, n, m, ld, centered, p, partS, partSum, partShift, srow, st);
     }
@@ -1561,6 +1653,7 @@ hipError_t launch_cov_partial(const void *Y, int dt, int64_t n, int m, int64_t l
         switch (mode) {
         case MODE_F32: return launch_dma4_m<MODE_F32>(y, n, m, ld, plan, partS, partSum, partShift, srow, st);
         case MODE_BF16X3: return launch_dma4_m<MODE_BF16X3>(y, n, m, ld, plan, partS, partSum, partShift, srow, st);
+        case MODE_FP16X3: return launch_dma4_m<MODE_FP16X3>(y, n, m, ld, plan, partS, partSum, partShift, srow, st);
         default: return launch_dma4_m<MODE_BF16X4>(y, n, m, ld, plan, partS, partSum, partShift, srow, st);
         }
     }
@@ -1604,10 +1697,12 @@ hipError_t launch_cov_batched(int dt, int mode, const char *ws, const int64_t to
     if (dt == PCA_IN_F32) {
         if (mode == MODE_F32) PCA_COV_BD(MODE_F32);
         else if (mode == MODE_BF16X3) PCA_COV_BD(MODE_BF16X3);
+        else if (mode == MODE_FP16X3) PCA_COV_BD(MODE_FP16X3);
         else PCA_COV_BD(MODE_BF16X4);
     } else {
         if (mode == MODE_F32) PCA_COV_B(uint16_t, MODE_F32);
         else if (mode == MODE_BF16X3) PCA_COV_B(uint16_t, MODE_BF16X3);
+        else if (mode == MODE_FP16X3) PCA_COV_B(uint16_t, MODE_FP16X3);
         else PCA_COV_B(uint16_t, MODE_BF16X4);
     }
 #undef PCA_COV_B

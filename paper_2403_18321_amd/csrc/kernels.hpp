@@ -27,7 +27,8 @@ struct CovPlan {
     size_t bytes_shift;  // per-chunk shifts, float32
     int groups;          // chunk groups of the first finalize pass
     size_t bytes_part2;  // float64 partial results of those groups + means
-    size_t bytes_srow;   // shift row: float32 [256], then the same row in the cube's type [256]
+    size_t bytes_srow;   // shift row: float32 [256], the same row in the cube's type [256], then the
+                         // float16 split's band scales sc [256] and 1 / sc [256]
 };
 CovPlan cov_plan(int64_t n, int m);
 
@@ -49,7 +50,7 @@ __host__ __device__ inline CovPlan cov_plan_chunk(int64_t n, int m, int64_t chun
     p.bytes_shift = (size_t)p.nchunks * p.mpad * sizeof(float);
     p.groups = (int)(p.nchunks < 8 ? p.nchunks : 8);
     p.bytes_part2 = ((size_t)p.groups * p.nblk * 1024 + 1 + 256) * sizeof(double);
-    p.bytes_srow = 2 * 256 * sizeof(float);
+    p.bytes_srow = 4 * 256 * sizeof(float);
     return p;
 }
 

@@ -48,6 +48,7 @@ def test_workspace_sizes(lib):
     a = L.pca_workspace_size(L.PCA_OP_COVARIANCE, 1 << 20, 224, mode=L.PCA_COV_BF16X3)
     b = L.pca_workspace_size(L.PCA_OP_COVARIANCE, 1 << 16, 224)
     assert a >= b > 0
+    assert L.pca_workspace_size(L.PCA_OP_COVARIANCE, 1 << 20, 224, mode=L.PCA_COV_FP16X3) == a
     j = L.pca_workspace_size(L.PCA_OP_JACOBI, 2, 224, max_sweeps=30)
     assert j >= 30 * 223 * 112 * 8
     assert L.pca_workspace_size(L.PCA_OP_PROJECT, 100, 10) == 0
@@ -73,6 +74,7 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert so.pca_covariance(fake, 0, 1, 8, 8, 0, null, 0, fake, fake, 1 << 20, null) == ARG
     assert so.pca_covariance(fake, 0, 100, 8, 7, 0, null, 0, fake, fake, 1 << 20, null) == ARG
     assert so.pca_covariance(fake, 0, 100, 8, 8, 0, null, 7, fake, fake, 1 << 20, null) == ARG
+    assert so.pca_covariance(fake, 0, 100, 8, 8, 0, null, lib.PCA_COV_FP16X3 + 1, fake, fake, 1 << 20, null) == ARG
     assert so.pca_covariance(fake, 5, 100, 8, 8, 0, null, 0, fake, fake, 1 << 20, null) == ARG
     # Workspace too small.
     assert so.pca_covariance(fake, 0, 100000, 64, 64, 0, null, 0, fake, fake, 256,

@@ -82,7 +82,7 @@ def check_against_oracle(P, b, cubes, ks, label):
         assert mu_err <= 1e-6
 
 
-@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3", "fp16x3"])
 def test_batched_matches_oracle(pca, mode):
     cubes, ks = small_batch()
     b = pca.BatchedPCA([dev(Y) for Y in cubes], ks, mode)

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 EIG_TOL = 1e-5
 ANGLE_TOL = 1e-4
 PROJ_TOL = 1e-4
-COV_TOL = {"f32": 2e-6, "bf16x4": 2e-6, "bf16x3": 3e-5}
+COV_TOL = {"f32": 2e-6, "bf16x4": 2e-6, "bf16x3": 3e-5, "fp16x3": 3e-6}
 
 
 def say(*a):
@@ -76,7 +76,7 @@ def test_bsq_covariance(pca, n, m, pad):
     Yb = bsq(Yh, pad)
     Yi = torch.from_numpy(Yh).cuda()
     scale = np.abs(ref["C"]).max()
-    for mode in ("f32", "bf16x3", "bf16x4"):
+    for mode in ("f32", "bf16x3", "bf16x4", "fp16x3"):
         C, mean = cov(pca, Yb, mode, "bsq")
         Ci, _ = cov(pca, Yi, mode, "bip")
         err = np.abs(C - ref["C"]).max() / scale
@@ -95,7 +95,7 @@ def test_bsq_uint16_and_centered(pca):
     # copies in the split forms
     for pad in (2, 8):
         Yb = bsq(u, pad)
-        for mode in ("f32", "bf16x3", "bf16x4"):
+        for mode in ("f32", "bf16x3", "bf16x4", "fp16x3"):
             C, mean = cov(pca, Yb, mode, "bsq")
             err = np.abs(C - ref["C"]).max() / np.abs(ref["C"]).max()
             say(f"  pad {pad} {mode}: {err:.2e}")
