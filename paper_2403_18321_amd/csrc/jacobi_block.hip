@@ -145,9 +145,19 @@ __device__ inline float4 make_rec(float app, float aqq, float apq, float floor_a
     const bool on = ad > floor_abs && ad * ad > 3.5527137e-15f * fabsf(app * aqq);   // |a_pq| > 2^-24 sqrt(|a_pp a_qq|)
     float tf;
     if constexpr (FP64) {
+        // sqrt and the quotient from the hardware float64 estimates (about
+        // single precision) refined by one Newton step each: relative error
+        // near 2^-44, far below the float32 rounding of the result, with a
+        // much shorter dependency chain than the correctly rounded forms.
+        // A zero x (no pivot) gives inf / NaN here, which `on` discards.
         const double d = (double)aqq - (double)app, a = (double)apq;
-        const double r = sqrt(fma(d, d, 4.0 * a * a));
-        tf = (float)((d >= 0.0 ? 2.0 * a : -2.0 * a) / (fabs(d) + r));
+        const double x = fma(d, d, 4.0 * a * a);
+        double y = __builtin_amdgcn_rsq(x);
+        y = y * fma(-0.5 * x * y, y, 1.5);
+        const double den = fabs(d) + x * y;
+        double q = __builtin_amdgcn_rcp(den);
+        q = q * fma(-den, q, 2.0);
+        tf = (float)((d >= 0.0 ? 2.0 * a : -2.0 * a) * q);
     } else {
         const float df = aqq - app;
         const float rf = __builtin_amdgcn_sqrtf(fmaf(df, df, 4.f * apq * apq));
