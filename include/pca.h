@@ -51,7 +51,7 @@ typedef enum {
  * sensors deliver it. Band-sequential (BSQ): Y[b * ld_y + p], ld_y >=
  * n_pixels, a band's pixels contiguous: the layout of the paper's GPU
  * design (Section 4). BSQ is accepted by pca_center, pca_covariance and
- * pca_project; pca_backward and pca_batched take BIP cubes. */
+ * pca_project, and in float32 by pca_backward; pca_batched takes BIP cubes. */
 typedef enum {
     PCA_IN_F32 = 0,           /* float32, BIP */
     PCA_IN_U16 = 1,           /* uint16 (e.g. raw radiance counts), read as exact integers, BIP */
@@ -272,7 +272,8 @@ pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands,
  * eigendecomposition; it assumes the eigenvalues that meet a nonzero F entry
  * (those among the first k and their partners) are distinct. The sign fix and
  * the sort of the forward pass are piecewise constant and add no term.
- *   Y        [n_pixels][ld_y] float32 cube, the forward input.
+ *   Y        the forward input: float32, dt PCA_IN_F32 ([n_pixels][ld_y],
+ *            BIP) or PCA_IN_F32_BSQ ([n_bands][ld_y], BSQ, ld_y >= n_pixels).
  *   mean     [n_bands] float32 band means written by the forward pass.
  *   eigvals  [n_bands] float32, V [n_bands][n_bands] float32 (column i =
  *            eigenvector i): the forward's eigenpairs.
@@ -280,12 +281,13 @@ pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands,
  *   dQ       [n_pixels][k] dL/dQ, or NULL (zero).
  *   dEig     [n_bands] dL/d eigvals, or NULL (zero).
  *   dVk      [n_bands][k] dL/dV[:, :k], or NULL (zero).
- *   dY       [n_pixels][ld_dy] float32 out, ld_dy >= n_bands.
+ *   dY       float32 out in the layout of Y: [n_pixels][ld_dy], ld_dy >=
+ *            n_bands (BIP), or [n_bands][ld_dy], ld_dy >= n_pixels (BSQ).
  *   ws       workspace of pca_workspace_size(PCA_OP_BACKWARD, n_pixels, n_bands, k, ...).
  * Float64 is used for every reduction over pixels and for the small
  * bands x bands algebra; the final pixel pass is a float32 MFMA product.
  */
-pca_status pca_backward(const float *Y, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,
+pca_status pca_backward(const float *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,
                         const float *eigvals, const float *V, int32_t k, const float *dQ, const float *dEig,
                         const float *dVk, float *dY, int64_t ld_dy, void *ws, size_t ws_bytes, void *stream);
 

@@ -90,7 +90,7 @@ def _lib() -> ctypes.CDLL:
         lib.pca_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.c_int, _f64, _i32, _i32, _vp, _vp, _sz,
                                     _vp]
         lib.pca_backward.restype = ctypes.c_int
-        lib.pca_backward.argtypes = [_vp, _i64, _i32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _sz,
+        lib.pca_backward.argtypes = [_vp, _i32, _i64, _i32, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _sz,
                                      _vp]
         _LIB = lib
     return _LIB
@@ -211,18 +211,20 @@ def _f32(name, t, shape):
         raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {tuple(shape)}")
 
 
-def pca_backward(Y, mean, eigvals, V, k: int, dY, dQ=None, dEig=None, dVk=None, ws=None):
-    dt, n, m, ld = _cube(Y)
-    if dt != PCA_IN_F32:
+def pca_backward(Y, mean, eigvals, V, k: int, dY, dQ=None, dEig=None, dVk=None, ws=None, layout: str = "bip"):
+    """dY in the layout of Y: [pixels, bands] ("bip") or [bands, pixels] ("bsq")."""
+    dt, n, m, ld = _cube(Y, layout)
+    if dt not in (PCA_IN_F32, PCA_IN_F32_BSQ):
         raise ValueError("pca_backward needs a float32 cube")
     for name, t, shape in (("mean", mean, (m,)), ("eigvals", eigvals, (m,)), ("V", V, (m, m)),
                            ("dQ", dQ, (n, k)), ("dEig", dEig, (m,)), ("dVk", dVk, (m, k))):
         _f32(name, t, shape)
-    if dY.dtype != torch.float32 or dY.dim() != 2 or tuple(dY.shape) != (n, m) or dY.stride(1) != 1:
-        raise ValueError("dY must be a float32 [pixels, bands] device tensor with unit band stride")
+    want = (m, n) if dt == PCA_IN_F32_BSQ else (n, m)
+    if dY.dtype != torch.float32 or dY.dim() != 2 or tuple(dY.shape) != want or dY.stride(1) != 1:
+        raise ValueError(f"dY must be a float32 {list(want)} device tensor with unit stride along its second axis")
     if ws is None:
         ws = workspace(pca_workspace_size(PCA_OP_BACKWARD, n, m, k=k), Y.device)
-    _check("pca_backward", _lib().pca_backward(_ptr(Y), n, m, ld, _ptr(mean), _ptr(eigvals), _ptr(V), int(k),
+    _check("pca_backward", _lib().pca_backward(_ptr(Y), dt, n, m, ld, _ptr(mean), _ptr(eigvals), _ptr(V), int(k),
                                                _ptr(dQ), _ptr(dEig), _ptr(dVk), _ptr(dY), dY.stride(0), _ptr(ws),
                                                ws.numel(), _stream()))
 

@@ -156,22 +156,44 @@ def run(Y: torch.Tensor, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
     return pipe.forward(Y)
 
 
+# Pipelines (and their workspaces) of the autograd Function, reused across
+# calls of the same shape and settings. A pipeline's calls go to the current
+# stream in order; its result tensors are cloned before they are handed out.
+_FN_PIPES = {}
+_FN_PIPES_MAX = 8
+
+
+def _fn_pipeline(n, m, k, mode, tol, max_sweeps, device, layout):
+    key = (str(device), n, m, k, mode, float(tol), int(max_sweeps), layout)
+    pipe = _FN_PIPES.get(key)
+    if pipe is None:
+        if len(_FN_PIPES) >= _FN_PIPES_MAX:
+            _FN_PIPES.pop(next(iter(_FN_PIPES)))
+        pipe = PCAPipeline(n, m, k, mode, tol, max_sweeps, True, device, layout=layout)
+        _FN_PIPES[key] = pipe
+    return pipe
+
+
 class PCAFunction(torch.autograd.Function):
     """(Q, eigvals, V[:, :k]) = PCA(Y) with the hand-written adjoint of
     pca_backward as its derivative. Forward: fused centring + covariance,
-    Jacobi eigenpairs, projection; backward: one pca_backward call."""
+    Jacobi eigenpairs, projection; backward: one pca_backward call. Y is
+    [pixels, bands] ("bip") or [bands, pixels] ("bsq"); its gradient has
+    the same layout."""
 
     @staticmethod
     def forward(ctx, Y, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
-                max_sweeps: int = DEFAULT_MAX_SWEEPS):
+                max_sweeps: int = DEFAULT_MAX_SWEEPS, layout: str = "bip"):
         if Y.dtype != torch.float32:
             raise ValueError("PCAFunction needs a float32 cube")
         Yc = Y.detach()
-        pipe = PCAPipeline(Yc.shape[0], Yc.shape[1], k, mode, tol, max_sweeps, True, Yc.device)
+        n, m = (Yc.shape[1], Yc.shape[0]) if layout == "bsq" else (Yc.shape[0], Yc.shape[1])
+        pipe = _fn_pipeline(n, m, k, mode, tol, max_sweeps, Yc.device, layout)
         r = pipe.forward(Yc)
         mean, eigvals, V = r.mean.clone(), r.eigvals.clone(), r.V.clone()
         ctx.save_for_backward(Yc, mean, eigvals, V)
         ctx.k = int(k)
+        ctx.layout = layout
         return r.Q.clone(), eigvals.clone(), V[:, :k].contiguous()
 
     @staticmethod
@@ -180,11 +202,11 @@ class PCAFunction(torch.autograd.Function):
         k = ctx.k
         dY = torch.empty_like(Y)
         prep = lambda t: None if t is None else t.detach().to(torch.float32).contiguous()
-        L.pca_backward(Y, mean, eigvals, V, k, dY, prep(dQ), prep(dEig), prep(dVk))
-        return dY, None, None, None, None
+        L.pca_backward(Y, mean, eigvals, V, k, dY, prep(dQ), prep(dEig), prep(dVk), layout=ctx.layout)
+        return dY, None, None, None, None, None
 
 
 def pca_autograd(Y: torch.Tensor, k: int, mode: str = "f32", tol: float = DEFAULT_TOL,
-                 max_sweeps: int = DEFAULT_MAX_SWEEPS):
+                 max_sweeps: int = DEFAULT_MAX_SWEEPS, layout: str = "bip"):
     """Differentiable PCA of a float32 device cube: returns (Q, eigvals, V_k)."""
-    return PCAFunction.apply(Y, k, mode, tol, max_sweeps)
+    return PCAFunction.apply(Y, k, mode, tol, max_sweeps, layout)

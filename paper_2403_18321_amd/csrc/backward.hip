@@ -29,6 +29,11 @@
 //               augmented K dimension staged through LDS 32 at a time (the
 //               next slab's loads in flight during the current one's
 //               products).
+// Band-sequential cubes (Y and dY [bands][pixels], the layout of the paper's
+// GPU design, Section 4) take the same kernels with the cube indexed the
+// other way; bwd_apply then forms dY^T = G^T [X | Qbar | 1]^T (the MFMA
+// operands swapped), so that a result register's lanes hold consecutive
+// pixels of one band and its stores stay coalesced.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -46,6 +51,7 @@ constexpr int kApplyPitch = kApplyK + 1;
 // Partial sums of one (chunk, component group): prod[M][8], sq[8], sx[M].
 __host__ __device__ inline int64_t part_stride(int m) { return 9 * (int64_t)m + kCompGroup; }
 
+template <bool BSQ>
 __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float *__restrict__ Y, int64_t n, int m,
                                                               int64_t ld, const float *__restrict__ mean,
                                                               const float *__restrict__ dQ, int k, int64_t chunk,
@@ -74,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float *__res
         if (hasb) {
 #pragma unroll 8
             for (int pp = 0; pp < np; ++pp) {
-                const double x = (double)(Y[(pt + pp) * ld + t] - mu);
+                const double x = (double)(Y[BSQ ? (int64_t)t * ld + pt + pp : (pt + pp) * ld + t] - mu);
                 sx += x;
 #pragma unroll
                 for (int j = 0; j < kCompGroup; ++j) acc[j] += x * (double)qt[pp][j];
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void bwd_r_kernel(int64_t n, int m, int k
 
 // NT: 32-column tiles of dY held per wave (4 for up to 128 bands, else 8;
 // fewer accumulators leave room for more waves per SIMD).
-template <int NT>
+template <int NT, bool BSQ>
 __global__ __launch_bounds__(kThreads, NT == 4 ? 2 : 1) void bwd_apply_kernel(const float *__restrict__ Y, int64_t n, int m,
                                                              int64_t ld, const float *__restrict__ mean,
                                                              const float *__restrict__ dQ, int k,
@@ -258,7 +264,7 @@ __global__ __launch_bounds__(kThreads, NT == 4 ? 2 : 1) void bwd_apply_kernel(co
             const int64_t p = base + pr0 + (kThreads / kApplyK) * i;
             float v = 0.f;
             if (p < n) {
-                if (c < m) v = Y[p * ld + c];
+                if (c < m) v = Y[BSQ ? (int64_t)c * ld + p : p * ld + c];
                 else if (c < m + k) v = dQ ? dQ[p * k + (c - m)] : 0.f;
                 else if (c == m + k) v = 1.f;
             }
@@ -291,22 +297,30 @@ __global__ __launch_bounds__(kThreads, NT == 4 ? 2 : 1) void bwd_apply_kernel(co
             for (int t = 0; t < NT; ++t) {
                 if (t < ntiles) {
                     const float b = Bt[kk * 256 + 32 * t + (lane & 31)];
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
+                    acc[t] = BSQ ? __builtin_amdgcn_mfma_f32_32x32x2f32(b, a, acc[t], 0, 0, 0)
+                                 : __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
                 }
             }
         }
     }
     // 32x32 result layout: lane l, register r -> row 8 (r/4) + 4 (l/32) + r%4,
-    // column l % 32.
+    // column l % 32 (rows pixels and columns bands; the other way round for
+    // band-sequential cubes).
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (t < ntiles) {
-            const int col = 32 * t + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                const int64_t p = base + 32 * wave + row;
-                if (p < n && col < m) dY[p * ldd + col] = acc[t][r];
+                if constexpr (BSQ) {
+                    const int band = 32 * t + row;
+                    const int64_t p = base + 32 * wave + (lane & 31);
+                    if (p < n && band < m) dY[(int64_t)band * ldd + p] = acc[t][r];
+                } else {
+                    const int col = 32 * t + (lane & 31);
+                    const int64_t p = base + 32 * wave + row;
+                    if (p < n && col < m) dY[p * ldd + col] = acc[t][r];
+                }
             }
         }
     }
@@ -333,25 +347,35 @@ BwdPlan bwd_plan(int64_t n, int m, int k)
     return p;
 }
 
-hipError_t launch_backward(const float *Y, int64_t n, int m, int64_t ld, const float *mean, const float *lam,
+hipError_t launch_backward(const float *Y, int bsq, int64_t n, int m, int64_t ld, const float *mean, const float *lam,
                            const float *V, int k, const float *dQ, const float *dEig, const float *dVk,
                            float *dY, int64_t ldd, const BwdPlan &p, double *part, double *wbuf, double *sums,
                            float *G, hipStream_t st)
 {
-    hipLaunchKernelGGL(bwd_reduce_kernel, dim3((unsigned)p.nchunks, (unsigned)p.kg), dim3(kThreads), 0, st, Y, n, m,
-                       ld, mean, dQ, k, p.chunk, p.kg, part);
+    const dim3 gr((unsigned)p.nchunks, (unsigned)p.kg);
+    if (bsq)
+        hipLaunchKernelGGL(bwd_reduce_kernel<true>, gr, dim3(kThreads), 0, st, Y, n, m, ld, mean, dQ, k, p.chunk, p.kg,
+                           part);
+    else
+        hipLaunchKernelGGL(bwd_reduce_kernel<false>, gr, dim3(kThreads), 0, st, Y, n, m, ld, mean, dQ, k, p.chunk, p.kg,
+                           part);
     hipLaunchKernelGGL(bwd_w_kernel, dim3((unsigned)(k + 1)), dim3(kWThreads), 0, st, m, k, p.nchunks, p.kg,
                        (const double *)part, lam, V, dVk, wbuf, sums);
     const unsigned tb = (unsigned)((m + 15) / 16);
     hipLaunchKernelGGL(bwd_g_kernel, dim3(tb, tb), dim3(kThreads), 0, st, n, m, k, V, dEig, (const double *)wbuf, G);
     hipLaunchKernelGGL(bwd_r_kernel, dim3(1), dim3(kThreads), 0, st, n, m, k, V, (const double *)sums, G);
     const dim3 ga((unsigned)((n + kApplyPix - 1) / kApplyPix));
-    if (m <= 128)
-        hipLaunchKernelGGL(bwd_apply_kernel<4>, ga, dim3(kThreads), 0, st, Y, n, m, ld, mean, dQ, k, (const float *)G, dY,
-                           ldd);
-    else
-        hipLaunchKernelGGL(bwd_apply_kernel<8>, ga, dim3(kThreads), 0, st, Y, n, m, ld, mean, dQ, k, (const float *)G, dY,
-                           ldd);
+#define PCA_BWD_APPLY(NT, B)                                                                                     \
+    hipLaunchKernelGGL((bwd_apply_kernel<NT, B>), ga, dim3(kThreads), 0, st, Y, n, m, ld, mean, dQ, k, (const float *)G, \
+                       dY, ldd)
+    if (m <= 128) {
+        if (bsq) PCA_BWD_APPLY(4, true);
+        else PCA_BWD_APPLY(4, false);
+    } else {
+        if (bsq) PCA_BWD_APPLY(8, true);
+        else PCA_BWD_APPLY(8, false);
+    }
+#undef PCA_BWD_APPLY
     return hipGetLastError();
 }
 

@@ -247,13 +247,16 @@ pca_status pca_project(const void *Y, int dt, int64_t n_pixels, int32_t n_bands,
                                           static_cast<hipStream_t>(stream)));
 }
 
-pca_status pca_backward(const float *Y, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,
+pca_status pca_backward(const float *Y, int dt, int64_t n_pixels, int32_t n_bands, int64_t ld_y, const float *mean,
                         const float *eigvals, const float *V, int32_t k, const float *dQ, const float *dEig,
                         const float *dVk, float *dY, int64_t ld_dy, void *ws, size_t ws_bytes, void *stream)
 {
-    pca_status s = check_cube(Y, PCA_IN_F32, n_pixels, n_bands, ld_y);
+    if (dt != PCA_IN_F32 && dt != PCA_IN_F32_BSQ) return PCA_ERR_ARG;
+    pca_status s = check_cube(Y, dt, n_pixels, n_bands, ld_y);
     if (s != PCA_OK) return s;
-    if (!mean || !eigvals || !V || !dY || !ws || k < 1 || k > n_bands || ld_dy < n_bands) return PCA_ERR_ARG;
+    const bool bsq = dt == PCA_IN_F32_BSQ;
+    if (!mean || !eigvals || !V || !dY || !ws || k < 1 || k > n_bands || ld_dy < (bsq ? n_pixels : (int64_t)n_bands))
+        return PCA_ERR_ARG;
     if (!aligned(mean, 4) || !aligned(eigvals, 4) || !aligned(V, 4) || !aligned(dY, 4) || !aligned(ws, kWsAlign))
         return PCA_ERR_ARG;
     if ((dQ && !aligned(dQ, 4)) || (dEig && !aligned(dEig, 4)) || (dVk && !aligned(dVk, 4))) return PCA_ERR_ARG;
@@ -267,7 +270,8 @@ pca_status pca_backward(const float *Y, int64_t n_pixels, int32_t n_bands, int64
     double *sums = reinterpret_cast<double *>(w);
     w += al(plan.bytes_sums);
     float *G = reinterpret_cast<float *>(w);
-    return hip_status(pca::launch_backward(Y, n_pixels, n_bands, ld_y, mean, eigvals, V, k, dQ, dEig, dVk, dY, ld_dy,
+    return hip_status(pca::launch_backward(Y, bsq ? 1 : 0, n_pixels, n_bands, ld_y, mean, eigvals, V, k, dQ, dEig, dVk,
+                                           dY, ld_dy,
                                            plan, part, wbuf, sums, G, static_cast<hipStream_t>(stream)));
 }
 

@@ -225,7 +225,7 @@ struct BwdPlan {
 };
 BwdPlan bwd_plan(int64_t n, int m, int k);
 
-hipError_t launch_backward(const float *Y, int64_t n, int m, int64_t ld, const float *mean, const float *lam,
+hipError_t launch_backward(const float *Y, int bsq, int64_t n, int m, int64_t ld, const float *mean, const float *lam,
                            const float *V, int k, const float *dQ, const float *dEig, const float *dVk,
                            float *dY, int64_t ldd, const BwdPlan &p, double *part, double *wbuf, double *sums,
                            float *G, hipStream_t st);

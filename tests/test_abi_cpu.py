@@ -106,14 +106,19 @@ def test_invalid_arguments_rejected_on_host(lib):
     # Projection: k out of range.
     assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 0, fake, null) == ARG
     assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 9, fake, null) == ARG
-    # Backward: k out of range, ld_dy < bands, NULL dY, workspace too small.
+    # Backward: k out of range, ld_dy < bands, NULL dY, workspace too small,
+    # a uint16 cube, a band-sequential dY stride below the pixel count.
     bw = so.pca_backward
-    assert bw(fake, 100, 8, 8, fake, fake, fake, 0, null, null, null, fake, 8, fake, 1 << 20, null) == ARG
-    assert bw(fake, 100, 8, 8, fake, fake, fake, 9, null, null, null, fake, 8, fake, 1 << 20, null) == ARG
-    assert bw(fake, 100, 8, 8, fake, fake, fake, 2, null, null, null, fake, 7, fake, 1 << 20, null) == ARG
-    assert bw(fake, 100, 8, 8, fake, fake, fake, 2, null, null, null, null, 8, fake, 1 << 20, null) == ARG
-    assert bw(fake, 100, 8, 8, fake, fake, fake, 2, fake, null, null, fake, 8, fake, 256,
+    F32, BSQ = lib.PCA_IN_F32, lib.PCA_IN_F32_BSQ
+    assert bw(fake, F32, 100, 8, 8, fake, fake, fake, 0, null, null, null, fake, 8, fake, 1 << 20, null) == ARG
+    assert bw(fake, F32, 100, 8, 8, fake, fake, fake, 9, null, null, null, fake, 8, fake, 1 << 20, null) == ARG
+    assert bw(fake, F32, 100, 8, 8, fake, fake, fake, 2, null, null, null, fake, 7, fake, 1 << 20, null) == ARG
+    assert bw(fake, F32, 100, 8, 8, fake, fake, fake, 2, null, null, null, null, 8, fake, 1 << 20, null) == ARG
+    assert bw(fake, F32, 100, 8, 8, fake, fake, fake, 2, fake, null, null, fake, 8, fake, 256,
               null) == lib.PCA_ERR_WORKSPACE
+    assert bw(fake, lib.PCA_IN_U16, 100, 8, 8, fake, fake, fake, 2, null, null, null, fake, 8, fake, 1 << 20,
+              null) == ARG
+    assert bw(fake, BSQ, 100, 8, 100, fake, fake, fake, 2, null, null, null, fake, 99, fake, 1 << 20, null) == ARG
 
 
 def test_batched_arguments_rejected_on_host(lib):

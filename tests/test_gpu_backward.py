@@ -186,6 +186,33 @@ def test_autograd_function(pca):
     assert rel(got, oracle_grad(Y, k, ct)) <= GRAD_TOL
 
 
+@pytest.mark.parametrize("n,m,k", [(5000, 40, 4), (9001, 160, 8)])
+def test_backward_band_sequential(pca, n, m, k):
+    """A band-sequential cube ([bands, pixels]) and its gradient in the same
+    layout: given the same forward eigenpairs, the transpose of the
+    band-interleaved gradient (same sums, the final product's operands
+    swapped); through the autograd Function, the FP64 adjoint."""
+    Y = planted(81 + m, n, m)
+    ct = cotangents(82 + m, n, m, k)
+    Yd = dev(Y)
+    Yb = Yd.t().contiguous()
+    r = pca.run(Yd, k)
+    c = [None if ct[w] is None else dev(ct[w]) for w in ("dQ", "dEig", "dVk")]
+    dY = torch.empty_like(Yd)
+    pca.pca_backward(Yd, r.mean, r.eigvals, r.V, k, dY, *c)
+    dYb = torch.empty_like(Yb)
+    pca.pca_backward(Yb, r.mean, r.eigvals, r.V, k, dYb, *c, layout="bsq")
+    a, b = host(dY), host(dYb).T
+    d = float(np.abs(a - b).max() / np.abs(a).max())
+    say(f"bsq backward n={n} m={m}: max diff {d:.2e} (bitwise {np.array_equal(a, b)})")
+    assert d <= 1e-6
+    Ybg = Yb.clone().requires_grad_(True)
+    Q, lam, Vk = pca.pca_autograd(Ybg, k, layout="bsq")
+    L = (Q * c[0]).sum() + (lam * c[1]).sum() + (Vk * c[2]).sum()
+    L.backward()
+    assert rel(host(Ybg.grad).T, oracle_grad(Y, k, ct)) <= GRAD_TOL
+
+
 def test_backward_rejects_wrong_dtype(pca):
     """The binding refuses float64 cotangents instead of reinterpreting them."""
     n, m, k = 500, 16, 3
