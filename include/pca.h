@@ -50,8 +50,7 @@ typedef enum {
  * Y[p * ld_y + b], ld_y >= n_bands, a pixel's bands contiguous, as push-broom
  * sensors deliver it. Band-sequential (BSQ): Y[b * ld_y + p], ld_y >=
  * n_pixels, a band's pixels contiguous: the layout of the paper's GPU
- * design (Section 4). BSQ is accepted by pca_center, pca_covariance and
- * pca_project, and in float32 by pca_backward; pca_batched takes BIP cubes. */
+ * design (Section 4). Every call takes BSQ cubes (pca_backward in float32). */
 typedef enum {
     PCA_IN_F32 = 0,           /* float32, BIP */
     PCA_IN_U16 = 1,           /* uint16 (e.g. raw radiance counts), read as exact integers, BIP */
@@ -123,9 +122,10 @@ typedef struct {
 
 /* One cube of a batch (pca_batched). Every pointer is a device pointer. */
 typedef struct {
-    const void *Y;       /* [n_pixels][ld_y] cube, element type given to pca_batched */
+    const void *Y;       /* the cube, element type and layout given to pca_batched:
+                            [n_pixels][ld_y] (BIP) or [n_bands][ld_y] (BSQ) */
     int64_t n_pixels;    /* >= 2 */
-    int64_t ld_y;        /* >= n_bands */
+    int64_t ld_y;        /* >= n_bands (BIP), >= n_pixels (BSQ) */
     int32_t n_bands;     /* 2 .. 256 */
     int32_t k;           /* kept components, 1 .. n_bands */
     float *mean;         /* [n_bands] out */
@@ -313,7 +313,8 @@ pca_status pca_batched_workspace_size(const pca_cube *cubes, int32_t n_cubes, in
  *   cubes_dev  the same array in device memory (read by the set-up kernel;
  *              keeping it resident makes the sequence capturable in a graph).
  *   n_cubes    1 .. 4096.
- *   dt         pca_in_dtype of every cube; mode a pca_cov_mode.
+ *   dt         pca_in_dtype of every cube (one element type and layout per
+ *              call); mode a pca_cov_mode.
  *   tol, max_sweeps, fp64_angles  as for pca_jacobi_eigh.
  *   tuning     tile shapes (NULL = defaults), e.g. from an autotuner.
  *   ws         workspace of pca_batched_workspace_size(...) bytes.

@@ -44,14 +44,18 @@ class BatchedPCA:
     holds all of them)."""
 
     def __init__(self, cubes, ks, mode: str = "f32", tol: float = DEFAULT_TOL,
-                 max_sweeps: int = DEFAULT_MAX_SWEEPS, fp64_angles: bool = True, tuning=None, lanes: int = 1):
+                 max_sweeps: int = DEFAULT_MAX_SWEEPS, fp64_angles: bool = True, tuning=None, lanes: int = 1,
+                 layout: str = "bip"):
+        """cubes: device tensors [pixels, bands] ("bip") or [bands, pixels]
+        ("bsq"), all of one element type and layout."""
         if not cubes:
             raise ValueError("empty batch")
         if isinstance(ks, int):
             ks = [ks] * len(cubes)
         if len(ks) != len(cubes):
             raise ValueError("one k per cube")
-        dts = {L._cube(Y)[0] for Y in cubes}
+        self.layout = layout
+        dts = {L._cube(Y, layout)[0] for Y in cubes}
         if len(dts) != 1:
             raise ValueError("all cubes of a batch must have the same element type")
         self.dt = dts.pop()
@@ -64,7 +68,7 @@ class BatchedPCA:
         self.mean, self.eigvals, self.V, self.Q, self.info = [], [], [], [], []
         descs = []
         for i, (Y, k) in enumerate(zip(self.cubes, self.ks)):
-            _, n, m, ld = L._cube(Y)
+            _, n, m, ld = L._cube(Y, layout)
             self.mean.append(torch.empty(m, **f32))
             self.eigvals.append(torch.empty(m, **f32))
             self.V.append(torch.empty(m, m, **f32))
@@ -72,7 +76,7 @@ class BatchedPCA:
             self.info.append(L.new_info(dev))
             descs.append(L.PCACube(Y.data_ptr(), n, ld, m, k, self.mean[i].data_ptr(), self.eigvals[i].data_ptr(),
                                    self.V[i].data_ptr(), self.Q[i].data_ptr(), self.info[i].data_ptr()))
-        self.groups = _lane_split([int(Y.shape[1]) for Y in self.cubes], int(lanes))
+        self.groups = _lane_split([L._cube(Y, layout)[2] for Y in self.cubes], int(lanes))
         self._host, self._dev = [], []
         for g in self.groups:
             arr = (L.PCACube * len(g))(*[descs[i] for i in g])

@@ -45,7 +45,9 @@ size_t jac_ws(const pca::JacPlan &p)
 }
 size_t bwd_ws(const pca::BwdPlan &p) { return al(p.bytes_part) + al(p.bytes_w) + al(p.bytes_sums) + al(p.bytes_g); }
 
-// Host-side checks and sizes of a batch; fills the six launch totals.
+// Host-side checks and sizes of a batch; fills the six launch totals. dt
+// kAnyU16 checks each cube as uint16 of whichever layout its stride allows.
+constexpr int kAnyU16 = -1;
 pca_status batch_plan(const pca_cube *cubes, int32_t n_cubes, int32_t max_sweeps, const pca_batch_tuning *tuning,
                       int dt, size_t *bytes, int64_t total[6], int *max_k, int *cov_chunk, int *proj_tiles)
 {
@@ -63,7 +65,8 @@ pca_status batch_plan(const pca_cube *cubes, int32_t n_cubes, int32_t max_sweeps
     int mk = 1;
     for (int32_t i = 0; i < n_cubes; ++i) {
         const pca_cube &c = cubes[i];
-        pca_status s = check_cube(c.Y, dt, c.n_pixels, c.n_bands, c.ld_y);
+        const int cdt = dt != kAnyU16 ? dt : (c.ld_y >= c.n_bands ? PCA_IN_U16 : PCA_IN_U16_BSQ);
+        pca_status s = check_cube(c.Y, cdt, c.n_pixels, c.n_bands, c.ld_y);
         if (s != PCA_OK) return s;
         if (c.k < 1 || c.k > c.n_bands || !c.mean || !c.eigvals || !c.V || !c.Q) return PCA_ERR_ARG;
         if (!aligned(c.mean, 4) || !aligned(c.eigvals, 4) || !aligned(c.V, 4) || !aligned(c.Q, 4)) return PCA_ERR_ARG;
@@ -280,17 +283,17 @@ pca_status pca_batched_workspace_size(const pca_cube *cubes, int32_t n_cubes, in
 {
     if (!bytes || mode < PCA_COV_F32 || mode > PCA_COV_FP16X3) return PCA_ERR_ARG;
     int64_t total[6];
-    // The element type does not change the sizes; check the cube pointers at
-    // the weaker (uint16) alignment here, pca_batched checks them again.
-    return batch_plan(cubes, n_cubes, max_sweeps, tuning, PCA_IN_U16, bytes, total, nullptr, nullptr, nullptr);
+    // Neither the element type nor the layout changes the sizes: check the
+    // cubes here as uint16 of either layout, pca_batched checks them again.
+    return batch_plan(cubes, n_cubes, max_sweeps, tuning, kAnyU16, bytes, total, nullptr, nullptr, nullptr);
 }
 
 pca_status pca_batched(const pca_cube *cubes, const pca_cube *cubes_dev, int32_t n_cubes, int dt, int mode,
                        double tol, int32_t max_sweeps, int32_t fp64_angles, const pca_batch_tuning *tuning,
                        void *ws, size_t ws_bytes, void *stream)
 {
-    if (is_bsq(dt)) return PCA_ERR_UNSUPPORTED;   // the batched form takes BIP cubes
-    if (!cubes_dev || !aligned(cubes_dev, 8) || !ws || !aligned(ws, kWsAlign) || !valid_dt(dt)) return PCA_ERR_ARG;
+    if (!cubes_dev || !aligned(cubes_dev, 8) || !ws || !aligned(ws, kWsAlign) || !(valid_dt(dt) || is_bsq(dt)))
+        return PCA_ERR_ARG;
     if (mode < PCA_COV_F32 || mode > PCA_COV_FP16X3) return PCA_ERR_ARG;
     if (!(tol >= 0.0) || !isfinite(tol) || (fp64_angles != 0 && fp64_angles != 1)) return PCA_ERR_ARG;
     size_t need = 0;

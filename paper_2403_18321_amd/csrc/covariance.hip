@@ -873,10 +873,10 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_dma4_kernel(
 constexpr int kBsqPitchF = 34;
 
 template <typename T, int MODE, int S>
-__global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
+__device__ __forceinline__ void cov_bsq_body(
     const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad, int idbase,
     float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
-    const float *__restrict__ srow)
+    const float *__restrict__ srow, int64_t c)
 {
     constexpr int kHalf = 256 * kBfPitch;
     __shared__ __attribute__((aligned(16))) float tileF[MODE == MODE_F32 ? 256 * kBsqPitchF : 4];
@@ -887,7 +887,6 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int pp = tid & 15;      // pixel pair within a stage
     const int bg = tid >> 4;      // band group: bands bg + 32 j
-    const int64_t c = blockIdx.x;
     const int64_t pbeg = c * chunk;
     const int64_t pend = (pbeg + chunk < n) ? pbeg + chunk : n;
     const int64_t nst = (pend - pbeg + KT - 1) / KT;
@@ -1030,6 +1029,16 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
             partShift[c * mpad + b] = sh[j];
         }
     }
+}
+
+template <typename T, int MODE, int S>
+__global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_kernel(
+    const T *__restrict__ Y, int64_t n, int m, int64_t ld, int64_t chunk, int nb, int nblk, int mpad, int idbase,
+    float *__restrict__ partS, double *__restrict__ partSum, float *__restrict__ partShift,
+    const float *__restrict__ srow)
+{
+    cov_bsq_body<T, MODE, S>(Y, n, m, ld, chunk, nb, nblk, mpad, idbase, partS, partSum, partShift, srow,
+                             (int64_t)blockIdx.x);
 }
 
 // Band-sequential cubes with 16-byte aligned band rows (ld and the pixel
@@ -1354,11 +1363,11 @@ __device__ inline int batch_find(const BatchCube *t, int nc, int64_t item)
 // Shift rows of every cube of a batch: workgroup (bb, r) takes band block bb
 // of the cube at table position r.
 template <typename T>
-__global__ __launch_bounds__(kShiftThreads) void cov_shift_batched_kernel(const char *ws)
+__global__ __launch_bounds__(kShiftThreads) void cov_shift_batched_kernel(const char *ws, int bsq)
 {
     const BatchCube &cb = batch_table(ws)[blockIdx.y];
     if ((int)blockIdx.x >= cb.cov.nb) return;
-    cov_shift_body<T>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, false, (int)blockIdx.x, cb.srow);
+    cov_shift_body<T>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, bsq != 0, (int)blockIdx.x, cb.srow);
 }
 
 template <typename T, int MODE>
@@ -1406,6 +1415,29 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_batched_dma_kernel(ch
         default: PCA_BATCH_BODY(5); break;
         }
 #undef PCA_BATCH_BODY
+    }
+}
+
+// Band-sequential cubes of the batch: the same queue over the register-staged
+// band-sequential chunk body, three slots a wave; a cube of more than 24
+// blocks takes its chunk in several passes (block ids 24 apart).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kDmaThreads) void cov_partial_batched_bsq_kernel(char *ws, int nc, int64_t total)
+{
+    __shared__ int64_t item_sh;
+    BatchHeader *h = reinterpret_cast<BatchHeader *>(ws);
+    const BatchCube *t = batch_table(ws);
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&h->counter[0], 1u);
+        __syncthreads();
+        const int64_t item = item_sh;
+        if (item >= total) break;
+        const BatchCube &cb = t[batch_find<&BatchCube::w_cov>(t, nc, item)];
+        for (int idbase = 0; idbase < cb.cov.nblk; idbase += 3 * kDmaWaves)
+            cov_bsq_body<T, MODE, 3>(static_cast<const T *>(cb.Y), cb.n, cb.m, cb.ld, cb.cov.chunk, cb.cov.nb,
+                                     cb.cov.nblk, cb.cov.mpad, idbase, cb.partS, cb.partSum, cb.partShift, cb.srow,
+                                     item - cb.w_cov);
     }
 }
 
@@ -1682,19 +1714,31 @@ hipError_t launch_cov_batched(int dt, int mode, const char *ws, const int64_t to
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
     // Register-staged uint16 kernel: two workgroups a CU; float32 copy
-    // kernel: one (its stage ring fills most of the LDS).
-    int64_t g = (int64_t)cus * (dt == PCA_IN_F32 ? 1 : 2);
+    // kernel: one (its stage ring fills most of the LDS); band-sequential
+    // kernel: one (eight waves of up to 256 registers).
+    int64_t g = (int64_t)cus * (dt == PCA_IN_U16 ? 2 : 1);
     if (g > total[0]) g = total[0];
     if (g < 1) g = 1;
     char *w = const_cast<char *>(ws);
     const dim3 grid((unsigned)g), block(kThreads), dgrid((unsigned)g), dblock(kDmaThreads);
     const dim3 sgrid(8u, (unsigned)n_cubes);
-    if (dt == PCA_IN_F32) hipLaunchKernelGGL(cov_shift_batched_kernel<float>, sgrid, dim3(kShiftThreads), 0, st, ws);
-    else hipLaunchKernelGGL(cov_shift_batched_kernel<uint16_t>, sgrid, dim3(kShiftThreads), 0, st, ws);
+    const int bsq = (dt == PCA_IN_F32_BSQ || dt == PCA_IN_U16_BSQ) ? 1 : 0;
+    if (dt == PCA_IN_F32 || dt == PCA_IN_F32_BSQ)
+        hipLaunchKernelGGL(cov_shift_batched_kernel<float>, sgrid, dim3(kShiftThreads), 0, st, ws, bsq);
+    else
+        hipLaunchKernelGGL(cov_shift_batched_kernel<uint16_t>, sgrid, dim3(kShiftThreads), 0, st, ws, bsq);
 #define PCA_COV_B(T, M)                                                                                           \
     hipLaunchKernelGGL((cov_partial_batched_kernel<T, M>), grid, block, 0, st, w, n_cubes, total[0])
 #define PCA_COV_BD(M) hipLaunchKernelGGL((cov_partial_batched_dma_kernel<M>), dgrid, dblock, 0, st, w, n_cubes, total[0])
-    if (dt == PCA_IN_F32) {
+#define PCA_COV_BB(T, M)                                                                                          \
+    hipLaunchKernelGGL((cov_partial_batched_bsq_kernel<T, M>), dgrid, dblock, 0, st, w, n_cubes, total[0])
+    if (dt == PCA_IN_F32_BSQ || dt == PCA_IN_U16_BSQ) {
+        const bool f = dt == PCA_IN_F32_BSQ;
+        if (mode == MODE_F32) { if (f) PCA_COV_BB(float, MODE_F32); else PCA_COV_BB(uint16_t, MODE_F32); }
+        else if (mode == MODE_BF16X3) { if (f) PCA_COV_BB(float, MODE_BF16X3); else PCA_COV_BB(uint16_t, MODE_BF16X3); }
+        else if (mode == MODE_FP16X3) { if (f) PCA_COV_BB(float, MODE_FP16X3); else PCA_COV_BB(uint16_t, MODE_FP16X3); }
+        else { if (f) PCA_COV_BB(float, MODE_BF16X4); else PCA_COV_BB(uint16_t, MODE_BF16X4); }
+    } else if (dt == PCA_IN_F32) {
         if (mode == MODE_F32) PCA_COV_BD(MODE_F32);
         else if (mode == MODE_BF16X3) PCA_COV_BD(MODE_BF16X3);
         else if (mode == MODE_FP16X3) PCA_COV_BD(MODE_FP16X3);
@@ -1707,6 +1751,7 @@ hipError_t launch_cov_batched(int dt, int mode, const char *ws, const int64_t to
     }
 #undef PCA_COV_B
 #undef PCA_COV_BD
+#undef PCA_COV_BB
     hipLaunchKernelGGL(cov_finalize_part_batched_kernel, dim3((unsigned)total[1]), dim3(1024), 0, st, ws, n_cubes);
     hipLaunchKernelGGL(cov_finalize_sum_batched_kernel, dim3((unsigned)total[2]), dim3(1024), 0, st, ws, n_cubes);
     return hipGetLastError();

@@ -198,15 +198,14 @@ hipError_t launch_t(const T *Y, int64_t n, int m, int64_t ld, const float *mean,
 // the block V[:, 16 g .. 16 g + 15] and the mean sit in LDS, where all lanes
 // read the same entry at a time (a broadcast). Float32 FMA chains per pixel,
 // bands in order.
+// Pixels p0, p0 + step, ... below p1, component group g.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void project_bsq_kernel(const T *__restrict__ Y, int64_t n, int m, int64_t ld,
-                                                               const float *__restrict__ mean,
-                                                               const float *__restrict__ V, int k,
-                                                               float *__restrict__ Q)
+__device__ __forceinline__ void project_bsq_body(const T *__restrict__ Y, int m, int64_t ld,
+                                                 const float *__restrict__ mean, const float *__restrict__ V, int k,
+                                                 float *__restrict__ Q, int g, int64_t p0, int64_t p1, int64_t step)
 {
     __shared__ __attribute__((aligned(16))) float vs[256][16];
     __shared__ float mu[256];
-    const int g = blockIdx.y;
     for (int e = threadIdx.x; e < 256 * 16; e += kThreads) {
         const int b = e >> 4, o = 16 * g + (e & 15);
         vs[b][e & 15] = (b < m && o < k) ? V[(int64_t)b * m + o] : 0.f;
@@ -214,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void project_bsq_kernel(const T *__restri
     for (int b = threadIdx.x; b < 256; b += kThreads) mu[b] = (mean && b < m) ? mean[b] : 0.f;
     __syncthreads();
     const int ncol = (k - 16 * g) < 16 ? (k - 16 * g) : 16;
-    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads) {
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += step) {
         float acc[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[j] = 0.f;
@@ -235,6 +234,38 @@ __global__ __launch_bounds__(kThreads) void project_bsq_kernel(const T *__restri
         for (int j = 0; j < 16; ++j)
             if (j < ncol) out[j] = acc[j];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void project_bsq_kernel(const T *__restrict__ Y, int64_t n, int m, int64_t ld,
+                                                               const float *__restrict__ mean,
+                                                               const float *__restrict__ V, int k,
+                                                               float *__restrict__ Q)
+{
+    project_bsq_body<T>(Y, m, ld, mean, V, k, Q, (int)blockIdx.y, (int64_t)blockIdx.x * kThreads, n,
+                        (int64_t)gridDim.x * kThreads);
+}
+
+// Batched band-sequential cubes: a work item is the same run of pixels as
+// project_batched_kernel's (proj_tiles 64-pixel tiles), one thread a pixel.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void project_batched_bsq_kernel(const char *ws, int nc)
+{
+    const BatchCube *t = reinterpret_cast<const BatchCube *>(ws + sizeof(BatchHeader));
+    const int64_t item = blockIdx.x;
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (t[mid].w_proj <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchCube &cb = t[lo];
+    const int g = blockIdx.y;
+    if (16 * g >= cb.k) return;
+    const int64_t per = (int64_t)cb.proj_tiles * kTP;
+    const int64_t p0 = (item - cb.w_proj) * per;
+    const int64_t p1 = (p0 + per < cb.n) ? p0 + per : cb.n;
+    project_bsq_body<T>(static_cast<const T *>(cb.Y), cb.m, cb.ld, cb.mean, cb.V, cb.k, cb.Q, g, p0, p1, kThreads);
 }
 
 template <typename T>
@@ -264,7 +295,11 @@ hipError_t launch_project_batched(int dt, const char *ws, const int64_t total[6]
                                   hipStream_t st)
 {
     const dim3 grid((unsigned)total[5], (unsigned)((max_k + 15) / 16)), block(kThreads);
-    if (dt == PCA_IN_F32)
+    if (dt == PCA_IN_F32_BSQ)
+        hipLaunchKernelGGL(project_batched_bsq_kernel<float>, grid, block, 0, st, ws, n_cubes);
+    else if (dt == PCA_IN_U16_BSQ)
+        hipLaunchKernelGGL(project_batched_bsq_kernel<uint16_t>, grid, block, 0, st, ws, n_cubes);
+    else if (dt == PCA_IN_F32)
         hipLaunchKernelGGL(project_batched_kernel<float>, grid, block, 0, st, ws, n_cubes);
     else
         hipLaunchKernelGGL(project_batched_kernel<uint16_t>, grid, block, 0, st, ws, n_cubes);

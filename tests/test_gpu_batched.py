@@ -90,6 +90,31 @@ def test_batched_matches_oracle(pca, mode):
     check_against_oracle(pca, b, cubes, ks, f"batched {mode}")
 
 
+@pytest.mark.parametrize("dtype,mode", [(np.float32, "f32"), (np.float32, "bf16x3"), (np.uint16, "fp16x3"),
+                                        (np.uint16, "bf16x4")])
+def test_batched_band_sequential(pca, dtype, mode):
+    """Band-sequential cubes ([bands, pixels]; one with a padded band stride)
+    through the batched form, against the oracle and against the same cubes
+    band-interleaved through the batched form."""
+    cubes, ks = small_batch(dtype)
+    bsq = []
+    for i, Y in enumerate(cubes):
+        if i == 1:
+            buf = np.zeros((Y.shape[1], Y.shape[0] + 5), dtype=Y.dtype)
+            buf[:, :Y.shape[0]] = Y.T
+            bsq.append(dev(buf)[:, :Y.shape[0]])
+        else:
+            bsq.append(dev(Y.T))
+    b = pca.BatchedPCA(bsq, ks, mode, layout="bsq")
+    b.run()
+    check_against_oracle(pca, b, cubes, ks, f"batched bsq {np.dtype(dtype).name} {mode}")
+    bb = pca.BatchedPCA([dev(Y) for Y in cubes], ks, mode)
+    bb.run()
+    for i in range(len(cubes)):
+        d = np.abs(host(b.eigvals[i]) - host(bb.eigvals[i])).max() / abs(host(bb.eigvals[i])).max()
+        assert d <= 1e-5, (i, d)
+
+
 def test_batched_uint16(pca):
     cubes, ks = small_batch(np.uint16)
     b = pca.BatchedPCA([dev(Y) for Y in cubes], ks, "bf16x3")
