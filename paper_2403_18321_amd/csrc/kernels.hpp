@@ -143,7 +143,7 @@ __host__ __device__ inline int follow_rows(int me)
 // ---- batched form ----------------------------------------------------------
 constexpr size_t kBatchAlign = 256;
 __host__ __device__ inline size_t batch_al(size_t x) { return (x + kBatchAlign - 1) / kBatchAlign * kBatchAlign; }
-constexpr int kBatchDefaultChunk = 8192;   // pixels per covariance work item
+constexpr int kBatchDefaultChunk = 4096;   // pixels per covariance work item
 constexpr int kBatchDefaultTiles = 16;     // 64-pixel tiles per projection work item
 constexpr int kProjTile = 64;
 
