@@ -36,7 +36,8 @@
 //      U's (float64 MFMA); waves 4-7 put the R and V operands in LDS;
 //   C. wave 0: the inner rotations on D, held in registers (below), which
 //      publish every step's rotations in LDS; waves 1-2: U_{t,x} from those
-//      rotations in float64, one step behind; waves 3-7: R = A_t[pair x,
+//      rotations in float64, one step behind; waves 3, 5-7 (wave 4 shares
+//      wave 0's SIMD and stays idle): R = A_t[pair x,
 //      pair j] = H_{t-1}[..] U_{t-1,j} (float64 MFMA), V_t[pair x rows, pair
 //      j cols] = V_{t-1}[..] U_{t-1,j} (float32 MFMA), and the tiles' shares
 //      of off(A_t)^2, ||A_t||_F^2;
@@ -865,7 +866,7 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
         __syncthreads();
         PROF(1);
 
-        // ---- C: inner rotations (wave 0), U (waves 1-2), other tiles (waves 3-7) --
+        // ---- C: inner rotations (wave 0), U (waves 1-2), other tiles (waves 3, 5-7)
 #ifdef BJ_PROFILE
         const long long tC = now_ticks();
 #endif
@@ -889,10 +890,14 @@ __device__ void bj_run(Smem &L, const BjArgs &A, int w, unsigned target0)
 #ifdef BJ_PROFILE
             if (lane == 0) L.prof_w[wave] = now_ticks() - tC;
 #endif
-        } else {
+        } else if (wave != 4) {
             // Tasks: 0-7 the R tiles of the column pairs (with their sums),
-            // 8-15 V tiles.
-            for (int task = wave - 3; task < 16; task += 5) {
+            // 8-15 V tiles, over waves 3, 5, 6, 7: wave 4 shares a SIMD with
+            // wave 0, whose inner steps are the critical path, and stays
+            // idle here so that they get its issue slots (1.52 -> 1.44 ms at
+            // 224 bands; the tasks, about 5 us a step, stay off the path).
+            const int slot = wave == 3 ? 0 : wave - 4;
+            for (int task = slot; task < 16; task += 4) {
                 const int jj = (task >> 2) & 1;
                 const int K = jj ? Kc[1] : Kc[0], Lb = jj ? Lc[1] : Lc[0];   // (selects, not an indexed array)
                 if (jj >= ncg) continue;
