@@ -301,8 +301,9 @@ pca_status pca_batched_workspace_size(const pca_cube *cubes, int32_t n_cubes, in
 /*
  * The whole pipeline (Algorithm 1) for many cubes of different pixel and
  * band counts, each as pca_covariance + pca_jacobi_eigh + pca_project would
- * compute it alone, in eight launches for the whole batch: a set-up kernel
- * that builds the task table in the workspace, one persistent covariance
+ * compute it alone, in nine launches for the whole batch: a set-up kernel
+ * that builds the task table in the workspace, the shift pass (a pixel
+ * sample per cube), one persistent covariance
  * launch whose workgroups take (cube, pixel chunk) items from a queue,
  * largest band counts first, the float64 chunk combination, a launch that
  * zeroes the rotation logs, one Jacobi launch with a workgroup per cube (each

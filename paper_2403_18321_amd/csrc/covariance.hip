@@ -20,11 +20,14 @@
 //
 // Pass-1 kernels by layout: cov_partial_dma_kernel (band-interleaved float32
 // or uint16 rows of whole 16-byte pieces, copied straight into LDS),
-// cov_partial_bsq_dma_kernel (band-sequential rows of whole 16-byte pieces,
-// split forms, likewise),
+// cov_partial_dma4_kernel (other band-interleaved float32 cubes, the same
+// kernel with 4-byte copies), cov_partial_bsq_dma_kernel (band-sequential
+// rows of whole 16-byte pieces, split forms, likewise),
 // cov_partial_bsq_kernel (other band-sequential cubes, register-staged),
-// cov_partial_kernel (any other band-interleaved layout, register-staged) and
-// cov_partial_batched_kernel (the batched form's persistent launch).
+// cov_partial_kernel (other band-interleaved uint16 layouts,
+// register-staged) and the batched form's persistent launches
+// (cov_partial_batched_dma_kernel, cov_partial_batched_bsq_kernel,
+// cov_partial_batched_kernel).
 #include "common.hpp"
 #include "kernels.hpp"
 #include "loader.hpp"
