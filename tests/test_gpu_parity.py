@@ -241,12 +241,14 @@ def test_projection_direct(pca):
 
 @pytest.mark.parametrize("n,m,k,u16", [(1000, 224, 10, False), (33, 64, 17, False), (70001, 256, 16, False),
                                        (5003, 224, 10, True), (777, 4, 3, False), (500, 2, 2, False),
-                                       (4096, 128, 32, False)])
+                                       (4096, 128, 32, False), (1001, 37, 5, False), (999, 255, 9, False),
+                                       (70003, 243, 5, False), (13, 3, 2, False)])
 def test_projection_shapes(pca, n, m, k, u16):
     """pca_project on aligned (4 bands a load) and unaligned rows, float32 and
     uint16, pixel counts that are not a multiple of the 32-pixel tile or that
     leave most workgroups without a tile, 1 to 64 K steps (the second band
-    half empty for 2 and 4 bands), and k up to two 16-column groups."""
+    half empty for 2 and 4 bands), k up to two 16-column groups, and odd
+    band counts up to 255 with ragged last tiles."""
     say(f"pca_project n={n} m={m} k={k} u16={u16}")
     rng = np.random.default_rng(n + m + k)
     if u16:
