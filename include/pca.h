@@ -324,6 +324,18 @@ pca_status pca_batched(const pca_cube *cubes, const pca_cube *cubes_dev, int32_t
                        double tol, int32_t max_sweeps, int32_t fp64_angles, const pca_batch_tuning *tuning,
                        void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * For tests of the failure handling only (callers that want a wait to run
+ * out without a fault): divides the time or poll bound of every wait inside
+ * the Jacobi kernels (the block-cyclic form's step barrier and its U
+ * followers' waits, the eigenvector followers of the overlapped replay and
+ * of the batched form) by 2^shift, 0 <= shift <= 40, on the current device;
+ * 0 restores the defaults. A wait that runs out ends its kernel normally and
+ * the call reports a non-finite result (or NaN eigenvector rows from a
+ * follower). Synchronous; not to be called while library work is in flight.
+ */
+pca_status pca_set_wait_shift(int32_t shift);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,7 @@ from ._lib import (  # noqa: F401
     pca_project,
     pca_workspace_size,
     read_info,
+    set_wait_shift,
     workspace,
 )
 from ._lib import PCABatchTuning, PCACube, pca_batched, pca_batched_workspace_size  # noqa: F401

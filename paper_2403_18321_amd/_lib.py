@@ -34,7 +34,7 @@ INFO_FIELDS = ("sweeps", "converged", "nonfinite", "floor_hit", "off_rel", "rota
 
 EXPORTS = ("pca_status_string", "pca_workspace_size", "pca_center", "pca_covariance",
            "pca_jacobi_eigh", "pca_jacobi_eigh_noalloc", "pca_project", "pca_backward", "pca_batched_workspace_size",
-           "pca_batched")
+           "pca_batched", "pca_set_wait_shift")
 
 
 class PCACube(ctypes.Structure):
@@ -86,6 +86,8 @@ def _lib() -> ctypes.CDLL:
         lib.pca_project.argtypes = [_vp, ctypes.c_int, _i64, _i32, _i64, _vp, _vp, _i32, _vp, _vp]
         lib.pca_batched_workspace_size.restype = ctypes.c_int
         lib.pca_batched_workspace_size.argtypes = [_vp, _i32, ctypes.c_int, _i32, _vp, ctypes.POINTER(_sz)]
+        lib.pca_set_wait_shift.restype = ctypes.c_int
+        lib.pca_set_wait_shift.argtypes = [_i32]
         lib.pca_batched.restype = ctypes.c_int
         lib.pca_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.c_int, _f64, _i32, _i32, _vp, _vp, _sz,
                                     _vp]
@@ -245,6 +247,13 @@ def pca_batched(cubes_host, cubes_dev, n_cubes: int, dt: int, mode: int, tol: fl
                               float(tol), int(max_sweeps), int(bool(fp64_angles)),
                               None if tuning is None else ctypes.cast(ctypes.pointer(tuning), _vp), _ptr(ws),
                               ws.numel(), _stream()))
+
+
+def set_wait_shift(shift: int):
+    """Divide the bounds of the Jacobi kernels' waits by 2^shift (tests of the
+    failure handling; 0 restores the defaults). Synchronises the device."""
+    torch.cuda.synchronize()
+    _check("pca_set_wait_shift", _lib().pca_set_wait_shift(int(shift)))
 
 
 def new_info(device=None) -> torch.Tensor:

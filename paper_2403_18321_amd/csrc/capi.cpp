@@ -312,4 +312,11 @@ pca_status pca_batched(const pca_cube *cubes, const pca_cube *cubes_dev, int32_t
     return hip_status(pca::launch_project_batched(dt, w, total, n_cubes, max_k, st));
 }
 
+pca_status pca_set_wait_shift(int32_t shift)
+{
+    if (shift < 0 || shift > 40) return PCA_ERR_ARG;
+    if (pca::set_wait_shift_one_cu(shift) != hipSuccess) return PCA_ERR_HIP;
+    return hip_status(pca::set_wait_shift_block(shift));
+}
+
 }  // extern "C"

@@ -661,6 +661,9 @@ __global__ __launch_bounds__(kReplayThreads) void vreplay_kernel(int n, int rows
 }
 
 constexpr int kFollowSpins = 1 << 19;   // polls of about 1 us on one entry before giving up
+// The followers' bound is divided by 2^g_wait_shift (0 unless a test of the
+// failure handling shortens it: pca_set_wait_shift).
+__device__ int g_wait_shift = 0;
 
 // Rows of E replayed beside the Jacobi workgroup (workgroup wg + 1 of the
 // launch): rows r0 .. r0+rows-1, in slot coordinates, double-buffered in the
@@ -687,6 +690,7 @@ __device__ __forceinline__ void follow_body(int n, int rows, const float2 *__res
     __syncthreads();
     int64_t done_steps = 0;
     int fail = 0;
+    const int spin_lim = kFollowSpins >> (g_wait_shift < 0 ? 0 : (g_wait_shift > 19 ? 19 : g_wait_shift));
     while (true) {
         // Wait for every entry of the batch (bounded), then count its steps
         // before the first end mark.
@@ -696,7 +700,7 @@ __device__ __forceinline__ void follow_body(int n, int rows, const float2 *__res
             float2 e = log_load(src);
             int spins = 0;
             while (__float_as_uint(e.x) == 0u && __float_as_uint(e.y) == 0u) {
-                if (++spins > kFollowSpins) { bad = 1; break; }
+                if (++spins > spin_lim) { bad = 1; break; }
                 __builtin_amdgcn_s_sleep(32);
                 e = log_load(src);
             }
@@ -964,6 +968,11 @@ hipError_t launch_jacobi_batched(const char *ws, const int64_t total[6], int n_c
                        n_cubes, tol, max_sweeps, fp64_angles);
     hipLaunchKernelGGL(sort_sign_batched_kernel, dim3((unsigned)total[4]), dim3(256), 0, st, ws, n_cubes);
     return hipGetLastError();
+}
+
+hipError_t set_wait_shift_one_cu(int shift)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_wait_shift), &shift, sizeof(int));
 }
 
 }  // namespace pca

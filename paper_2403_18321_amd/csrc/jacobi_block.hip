@@ -106,6 +106,10 @@ constexpr int kTiled = 32 * kLdd;
 constexpr int kNS = 31;        // inner steps of the first outer step of a sweep
 constexpr int kCg = kBjMaxColPairs;   // column pairs per workgroup, at most
 constexpr long long kWaitTicks = 50000000;   // 0.5 s of the 100 MHz real-time counter
+// Every bounded wait of this file is divided by 2^g_wait_shift (0 unless a
+// test of the failure handling shortens them: pca_set_wait_shift).
+__device__ int g_wait_shift = 0;
+__device__ inline int wait_shift() { const int s = g_wait_shift; return s < 0 ? 0 : (s > 40 ? 40 : s); }
 constexpr unsigned kRsrcWord3 = 0x00020000u;  // raw buffer resource, gfx9 family
 
 struct BjPart {
@@ -352,6 +356,7 @@ __device__ void grid_sync(Smem &L, unsigned *flags, int w, int G, unsigned targe
         else __hip_atomic_store(&flags[w], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid < 64) {
+        const int shift = wait_shift();
         const long long t0 = now_ticks();
         int anybad = 0, fail = 0;
         while (true) {
@@ -360,7 +365,7 @@ __device__ void grid_sync(Smem &L, unsigned *flags, int w, int G, unsigned targe
                 v = kLocal ? poll_local(&flags[lane])
                            : __hip_atomic_load(&flags[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (__all((v >> 1) >= target)) { anybad = __any((v & 1u) != 0u); break; }
-            if (now_ticks() - t0 > kWaitTicks) { fail = 1; break; }
+            if (now_ticks() - t0 > (kWaitTicks >> shift)) { fail = 1; break; }
         }
         if (lane == 0) {
             if (anybad) L.st_bad = 1;
@@ -487,9 +492,10 @@ __device__ inline void publish(Smem &L, int n)
 __device__ inline bool wait_pub(Smem &L, int s)
 {
     int spins = 0;
+    const int lim = (1 << 22) >> (wait_shift() > 22 ? 22 : wait_shift());
     while (__hip_atomic_load(&L.pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= s) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1 << 22)) return false;
+        if (++spins > lim) return false;
     }
     asm volatile("" ::: "memory");
     return true;
@@ -1103,6 +1109,11 @@ hipError_t launch_jacobi_block(const float *C, int m, double tol, int max_sweeps
     hipLaunchKernelGGL(bj_clear_kernel, dim3(1), dim3(64), 0, st, a.flags, 2 * G);
     hipLaunchKernelGGL(bj_kernel, dim3((unsigned)(8 * G)), dim3(kThreads), 0, st, a, res);
     return hipGetLastError();
+}
+
+hipError_t set_wait_shift_block(int shift)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_wait_shift), &shift, sizeof(int));
 }
 
 }  // namespace pca

@@ -242,6 +242,10 @@ hipError_t launch_jacobi_block(const float *C, int m, double tol, int max_sweeps
                                double *lam_u, float *VuT, int nvu, pca_info *info_ws, hipStream_t st);
 hipError_t launch_sort_sign(int m, int n, const double *lam_u, const float *Vu, const pca_info *info_ws,
                             float *eigvals, float *V, pca_info *info_out, hipStream_t st);
+// Divides the bounded waits of the Jacobi kernels by 2^shift (tests of the
+// failure handling; synchronous copies to the current device).
+hipError_t set_wait_shift_one_cu(int shift);
+hipError_t set_wait_shift_block(int shift);
 
 // ---- projection ------------------------------------------------------------
 hipError_t launch_project(const void *Y, int dt, int64_t n, int m, int64_t ld, const float *mean,

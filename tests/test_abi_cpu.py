@@ -106,6 +106,8 @@ def test_invalid_arguments_rejected_on_host(lib):
     # Projection: k out of range.
     assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 0, fake, null) == ARG
     assert so.pca_project(fake, 0, 100, 8, 8, null, fake, 9, fake, null) == ARG
+    # Wait shift out of range (checked before any device call).
+    assert so.pca_set_wait_shift(-1) == ARG and so.pca_set_wait_shift(41) == ARG
     # Backward: k out of range, ld_dy < bands, NULL dY, workspace too small,
     # a uint16 cube, a band-sequential dY stride below the pixel count.
     bw = so.pca_backward
