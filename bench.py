@@ -408,8 +408,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the pixel-sharded design is described in the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path, "
+              "so runs on more than one GPU are not made.", file=sys.stderr)
         return 2
 
     import numpy as np

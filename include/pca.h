@@ -41,7 +41,7 @@ extern "C" {
 typedef enum {
     PCA_OK = 0,
     PCA_ERR_ARG = 1,          /* NULL pointer, size out of range, misalignment */
-    PCA_ERR_UNSUPPORTED = 2,  /* valid request that this build does not handle */
+    PCA_ERR_UNSUPPORTED = 2,  /* valid request that the library does not handle */
     PCA_ERR_WORKSPACE = 3,    /* workspace smaller than pca_workspace_size */
     PCA_ERR_HIP = 4           /* a HIP launch or attribute call failed */
 } pca_status;

@@ -21,9 +21,10 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpca.so")
 
 ARCH = "gfx950"
-# Packed FP32 instructions are disabled for all device code (see the design
-# notes on the GPU pool); the host pass warns that it does not know the
-# feature, which is harmless.
+# Packed FP32 instructions (v_pk_*_f32) are disabled for all device code:
+# some of their forms have been seen to give wrong results now and then,
+# with no error. The host pass warns that it does not know the feature,
+# which is harmless.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-function"]

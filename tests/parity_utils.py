@@ -1,6 +1,6 @@
 """Comparison rules between GPU results and the FP64 oracle.
 
-Readings of the accuracy targets (also in the design notes):
+Readings of the accuracy targets:
   - eigenvalues: normwise, max_i |lam_hat_i - lam_i| / lam_1;
   - eigenvectors: only principal components that are well separated,
     min(lam_{i-1} - lam_i, lam_i - lam_{i+1}) >= g lam_1 with g = 1e-3, are
