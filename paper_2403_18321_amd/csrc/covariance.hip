@@ -546,7 +546,9 @@ __device__ __forceinline__ void lds_barrier()
 // LDS of the chunk kernel: one set per (element type, mode), shared by the
 // slot-count variants that one persistent launch inlines. The three ring
 // slots are separate LDS arrays, which lets the compiler see that reading
-// one slot does not wait on the copies into the others.
+// one slot does not wait on the copies into the others. The float32 form
+// uses three ring slots; the split forms two ring slots and two sets of
+// hi / lo tiles (stage k's tiles are read while stage k + 1's are written).
 template <typename T, int MODE>
 struct DmaLds {
     static constexpr int kPitch = (MODE == MODE_F32 && sizeof(T) == 4) ? 288 : 256;
@@ -557,6 +559,7 @@ struct DmaLds {
         __shared__ __attribute__((aligned(16))) T r[kRawElems];
         return r;
     }
+    template <int K>
     __device__ static __forceinline__ __bf16 *tiles()
     {
         __shared__ __attribute__((aligned(16))) __bf16 h[MODE == MODE_F32 ? 8 : 2 * 256 * kBfPitch];
@@ -596,8 +599,6 @@ __device__ __forceinline__ void cov_dma_body(
     constexpr int kRawWords = (kRawElems * (int)sizeof(T) + 3) / 4;
     T *const raw0 = DmaLds<T, MODE>::template ring<0>();
     T *const raw1 = DmaLds<T, MODE>::template ring<1>();
-    T *const raw2 = DmaLds<T, MODE>::template ring<2>();
-    __bf16 *const hl = DmaLds<T, MODE>::tiles();
     float *const shv = DmaLds<T, MODE>::shift();
     static_assert(kRawElems == DmaLds<T, MODE>::kRawElems, "ring slot size");
     static_assert(kRawWords * 4 >= kDmaWaves * 256 * (int)sizeof(double), "band-sum scratch");
@@ -716,7 +717,7 @@ __device__ __forceinline__ void cov_dma_body(
     // This wave's pixels of a landed stage, centred: band sums (float32 over
     // the stage's 4 pixels, then float64) and, for the split forms, the hi /
     // lo tiles in LDS, band-major.
-    auto centre = [&](const T *R) {
+    auto centre = [&](const T *R, __bf16 *hl) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int b = lane + 64 * s;
@@ -743,7 +744,7 @@ __device__ __forceinline__ void cov_dma_body(
         }
     };
 
-    auto products = [&](const T *R) {
+    auto products = [&](const T *R, const __bf16 *hl) {
         if constexpr (MODE == MODE_F32) {
 #pragma unroll 2
             for (int kk = 0; kk < KT / 2; ++kk) {
@@ -769,15 +770,11 @@ __device__ __forceinline__ void cov_dma_body(
         }
     };
 
-    // One stage in ring slot `cur`; the copies for two stages ahead go into
-    // `nxt` (the slot of the previous stage, which every wave has finished
-    // reading once past the first barrier). The stage count is rounded up to
-    // a multiple of the ring: stages past the chunk end are copies of its
-    // first pixel, which centre to exact zeros and add nothing, so every step
-    // is the same straight-line code with one copy wait.
-    auto step = [&](T *cur, T *nxt, int64_t st) {
+    // Wait until this wave's copies of the oldest stage in flight have landed
+    // (the copies of the stage after it may still be in flight).
+    auto wait_one = [&]() {
         if constexpr (CW == 4) {
-            switch (nq) {   // the copies of the stage after this one may still be in flight
+            switch (nq) {
             case 1: __builtin_amdgcn_s_waitcnt(waitcnt_vm(kDmaPix)); break;
             case 2: __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * kDmaPix)); break;
             case 3: __builtin_amdgcn_s_waitcnt(waitcnt_vm(3 * kDmaPix)); break;
@@ -786,12 +783,21 @@ __device__ __forceinline__ void cov_dma_body(
         } else {
             __builtin_amdgcn_s_waitcnt(waitcnt_vm(kCopies));
         }
-        lds_barrier();
-        issue(nxt, st + 2);
-        centre(cur);
-        if constexpr (MODE != MODE_F32) lds_barrier();
-        if (!kSkip || nbl > wave) products(cur);
-        if constexpr (kTwoLevel) {
+    };
+    // Stage counts are rounded up to a multiple of the ring: stages past the
+    // chunk end are copies of its first pixel, which centre to exact zeros
+    // and add nothing, so every step is the same straight-line code.
+    if constexpr (MODE == MODE_F32) {
+        // One stage in ring slot `cur`; the copies for two stages ahead go
+        // into `nxt` (the slot of the previous stage, which every wave has
+        // finished reading once past the barrier).
+        T *const raw2 = DmaLds<T, MODE>::template ring<2>();
+        auto step = [&](T *cur, T *nxt, int64_t st) {
+            wait_one();
+            lds_barrier();
+            issue(nxt, st + 2);
+            centre(cur, nullptr);
+            if (!kSkip || nbl > wave) products(cur, nullptr);
             if ((st + 1) % kFlush == 0) {
 #pragma unroll
                 for (int e = 0; e < S; ++e) {
@@ -799,13 +805,42 @@ __device__ __forceinline__ void cov_dma_body(
                     for (int r = 0; r < 16; ++r) { acc2[e][r] += acc[e][r]; acc[e][r] = 0.f; }
                 }
             }
+        };
+        for (int64_t st = 0; st < nst; st += kRing) {
+            step(raw0, raw2, st);
+            step(raw1, raw0, st + 1);
+            step(raw2, raw1, st + 2);
         }
-    };
-
-    for (int64_t st = 0; st < nst; st += kRing) {
-        step(raw0, raw2, st);
-        step(raw1, raw0, st + 1);
-        step(raw2, raw1, st + 2);
+    } else {
+        // Split forms: two ring slots and two tile sets. Step k centres stage
+        // k + 1 (its raw slot to tile set (k + 1) mod 2) and multiplies stage
+        // k (tile set k mod 2), with one barrier: the tiles written in step k
+        // are read in step k + 1, and the tile set read in step k is written
+        // again in step k + 1. Each wave centres only the rows its own copies
+        // bring in, so a raw slot needs only this wave's copy wait, and the
+        // copies for stage k + 2 may go into stage k's slot once this wave
+        // has centred it. Waves 4-7 multiply before they centre, so that the
+        // two waves of a SIMD (w and w + 4) overlap one's centring and
+        // splitting (vector ALU) with the other's products (matrix cores).
+        __bf16 *const t0 = DmaLds<T, MODE>::template tiles<0>();
+        __bf16 *const t1 = DmaLds<T, MODE>::template tiles<1>();
+        const bool prod_first = (wave & 4) != 0;
+        const bool has_blocks = !kSkip || nbl > wave;
+        wait_one();
+        centre(raw0, t0);
+        lds_barrier();
+        auto step = [&](T *slot_k, T *slot_k1, const __bf16 *tk, __bf16 *tk1, int64_t k) {
+            issue(slot_k, k + 2);
+            if (prod_first && has_blocks) products(nullptr, tk);
+            wait_one();
+            centre(slot_k1, tk1);
+            if (!prod_first && has_blocks) products(nullptr, tk);
+            lds_barrier();
+        };
+        for (int64_t k = 0; k < nst; k += 2) {
+            step(raw0, raw1, t0, t1, k);
+            step(raw1, raw0, t1, t0, k + 1);
+        }
     }
     // The stages copied ahead past the end must land before the workgroup's
     // LDS is reused (the band sums below, or another workgroup).
@@ -1249,8 +1284,20 @@ __device__ __forceinline__ void cov_finalize_part_body(
         const int64_t w0 = (int64_t)r * nchunks / 16, w1 = (int64_t)(r + 1) * nchunks / 16;
         double a = 0.0;
         if (b < m && !centered) {
-            for (int64_t w = w0; w < w1; ++w)
-                a += pixels(w) * (double)partShift[w * mpad + b] + partSum[w * mpad + b];
+            // Eight chunks' loads in flight at once, added in chunk order.
+            for (int64_t w = w0; w < w1; w += 8) {
+                float hv[8];
+                double sv8[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t wi = w + i < w1 ? w + i : w0;
+                    hv[i] = partShift[wi * mpad + b];
+                    sv8[i] = partSum[wi * mpad + b];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (w + i < w1) a += pixels(w + i) * (double)hv[i] + sv8[i];
+            }
         }
         mred[r][lane] = a;
     }
