@@ -746,25 +746,61 @@ __device__ __forceinline__ void cov_dma_body(
 
     auto products = [&](const T *R, const __bf16 *hl) {
         if constexpr (MODE == MODE_F32) {
-#pragma unroll 2
-            for (int kk = 0; kk < KT / 2; ++kk) {
-                const T *tr = R + (2 * kk + (lane >> 5)) * pitch;
+            // The operands of pixel pair kk + 1 are read while the products
+            // of pair kk run, so that no product waits for its LDS reads.
+            float xa[S], xb[S];
 #pragma unroll
-                for (int e = 0; e < S; ++e) {
-                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(load_elem(tr + offI[e]) - shI[e],
-                                                                 load_elem(tr + offJ[e]) - shJ[e], acc[e], 0, 0, 0);
+            for (int e = 0; e < S; ++e) {
+                xa[e] = load_elem(R + (lane >> 5) * pitch + offI[e]);
+                xb[e] = load_elem(R + (lane >> 5) * pitch + offJ[e]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < KT / 2; ++kk) {
+                float ya[S], yb[S];
+                if (kk + 1 < KT / 2) {
+                    const T *tr = R + (2 * kk + 2 + (lane >> 5)) * pitch;
+#pragma unroll
+                    for (int e = 0; e < S; ++e) {
+                        ya[e] = load_elem(tr + offI[e]);
+                        yb[e] = load_elem(tr + offJ[e]);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+#pragma unroll
+                for (int e = 0; e < S; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[e] - shI[e], xb[e] - shJ[e], acc[e], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (kk + 1 < KT / 2) {
+#pragma unroll
+                    for (int e = 0; e < S; ++e) {
+                        xa[e] = ya[e];
+                        xb[e] = yb[e];
+                    }
                 }
             }
         } else {
+            // (k-step, slot) items in order; the operands of the next item
+            // are read while the products of this one run.
+            constexpr int kItems = (KT / 16) * S;
+            bf16x8 cur[4], nxt[4];
+            auto operands = [&](int it, bf16x8(&o)[4]) {
+                const int kk = it / S, e = it - (it / S) * S;
+                o[0] = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
+                o[1] = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
+                o[2] = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
+                o[3] = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
+            };
+            operands(0, cur);
 #pragma unroll
-            for (int kk = 0; kk < KT / 16; ++kk) {
+            for (int it = 0; it < kItems; ++it) {
+                if (it + 1 < kItems) operands(it + 1, nxt);
+                __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+                const int e = it - (it / S) * S;
+                acc[e] = split_products<MODE>(cur[0], cur[1], cur[2], cur[3], acc[e]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (it + 1 < kItems) {
 #pragma unroll
-                for (int e = 0; e < S; ++e) {
-                    const bf16x8 hi_i = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
-                    const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
-                    const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
-                    const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
-                    acc[e] = split_products<MODE>(hi_i, lo_i, hi_j, lo_j, acc[e]);
+                    for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
                 }
             }
         }
