@@ -498,6 +498,39 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
                                       (int64_t)blockIdx.x);
 }
 
+// The split products of one 32-pixel stage for a wave's S blocks, from the
+// hi / lo tiles in LDS (hi at hl, lo kHalf further; block e's operand rows at
+// offI[e], offJ[e]). The (k-step, block) items run in order, and the
+// operands of the next item are read while the products of this one run.
+template <int MODE, int S>
+__device__ __forceinline__ void split_block_products(const __bf16 *hl, const int (&offI)[S], const int (&offJ)[S],
+                                                     f32x16 (&acc)[S])
+{
+    constexpr int kHalf = 256 * kBfPitch;
+    constexpr int kItems = (KT / 16) * S;
+    bf16x8 cur[4], nxt[4];
+    auto operands = [&](int it, bf16x8(&o)[4]) {
+        const int kk = it / S, e = it - (it / S) * S;
+        o[0] = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
+        o[1] = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
+        o[2] = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
+        o[3] = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
+    };
+    operands(0, cur);
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        if (it + 1 < kItems) operands(it + 1, nxt);
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+        const int e = it - (it / S) * S;
+        acc[e] = split_products<MODE>(cur[0], cur[1], cur[2], cur[3], acc[e]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (it + 1 < kItems) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
+        }
+    }
+}
+
 // ---- float32 cubes with 16-byte aligned rows: pixel rows copied into LDS --
 //
 // The same chunk algorithm, organised for this case:
@@ -779,30 +812,7 @@ __device__ __forceinline__ void cov_dma_body(
                 }
             }
         } else {
-            // (k-step, slot) items in order; the operands of the next item
-            // are read while the products of this one run.
-            constexpr int kItems = (KT / 16) * S;
-            bf16x8 cur[4], nxt[4];
-            auto operands = [&](int it, bf16x8(&o)[4]) {
-                const int kk = it / S, e = it - (it / S) * S;
-                o[0] = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
-                o[1] = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
-                o[2] = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
-                o[3] = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
-            };
-            operands(0, cur);
-#pragma unroll
-            for (int it = 0; it < kItems; ++it) {
-                if (it + 1 < kItems) operands(it + 1, nxt);
-                __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
-                const int e = it - (it / S) * S;
-                acc[e] = split_products<MODE>(cur[0], cur[1], cur[2], cur[3], acc[e]);
-                __builtin_amdgcn_sched_barrier(0);
-                if (it + 1 < kItems) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
-                }
-            }
+            split_block_products<MODE, S>(hl, offI, offJ, acc);
         }
     };
 
@@ -1052,17 +1062,7 @@ __device__ __forceinline__ void cov_bsq_body(
                 }
             }
         } else {
-#pragma unroll
-            for (int kk = 0; kk < KT / 16; ++kk) {
-#pragma unroll
-                for (int e = 0; e < S; ++e) {
-                    const bf16x8 hi_i = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
-                    const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
-                    const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
-                    const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
-                    acc[e] = split_products<MODE>(hi_i, lo_i, hi_j, lo_j, acc[e]);
-                }
-            }
+            split_block_products<MODE, S>(hl, offI, offJ, acc);
         }
         __syncthreads();
     };
@@ -1230,19 +1230,7 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
         }
     };
 
-    auto products = [&]() {
-#pragma unroll
-        for (int kk = 0; kk < KT / 16; ++kk) {
-#pragma unroll
-            for (int e = 0; e < S; ++e) {
-                const bf16x8 hi_i = *reinterpret_cast<const bf16x8 *>(&hl[offI[e] + 16 * kk]);
-                const bf16x8 lo_i = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offI[e] + 16 * kk]);
-                const bf16x8 hi_j = *reinterpret_cast<const bf16x8 *>(&hl[offJ[e] + 16 * kk]);
-                const bf16x8 lo_j = *reinterpret_cast<const bf16x8 *>(&hl[kHalf + offJ[e] + 16 * kk]);
-                acc[e] = split_products<MODE>(hi_i, lo_i, hi_j, lo_j, acc[e]);
-            }
-        }
-    };
+    auto products = [&]() { split_block_products<MODE, S>(hl, offI, offJ, acc); };
 
     // As in cov_partial_dma_kernel: wait for this stage's copies, barrier,
     // start the copies two stages ahead into the slot read last step,
