@@ -131,6 +131,8 @@ struct Smem {
     double red[2][2 * kCg * 4];   // per-tile off and total sums of squares of R
     int pub;               // inner steps whose records are published (wave 0 to waves 1-2)
     int st_bad, st_cnt, st_fail;
+    int pub_spins;         // bound of waves 1-2's wait for a record, in polls
+    long long wait_ticks;  // bound of a grid barrier wait, in real-time counter ticks
 #ifdef BJ_PROFILE
     long long prof_w[8];
 #endif
@@ -356,16 +358,21 @@ __device__ void grid_sync(Smem &L, unsigned *flags, int w, int G, unsigned targe
         else __hip_atomic_store(&flags[w], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid < 64) {
-        const int shift = wait_shift();
+        const long long lim = L.wait_ticks;
         const long long t0 = now_ticks();
         int anybad = 0, fail = 0;
-        while (true) {
-            unsigned v = target << 1;
-            if (lane < G)
-                v = kLocal ? poll_local(&flags[lane])
-                           : __hip_atomic_load(&flags[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (__all((v >> 1) >= target)) { anybad = __any((v & 1u) != 0u); break; }
-            if (now_ticks() - t0 > (kWaitTicks >> shift)) { fail = 1; break; }
+        bool done = false;
+        while (!done) {
+            // Eight polls between reads of the clock, so that the clock's
+            // latency does not lengthen every poll.
+            for (int i = 0; i < 8; ++i) {
+                unsigned v = target << 1;
+                if (lane < G)
+                    v = kLocal ? poll_local(&flags[lane])
+                               : __hip_atomic_load(&flags[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__all((v >> 1) >= target)) { anybad = __any((v & 1u) != 0u); done = true; break; }
+            }
+            if (!done && now_ticks() - t0 > lim) { fail = 1; break; }
         }
         if (lane == 0) {
             if (anybad) L.st_bad = 1;
@@ -492,7 +499,7 @@ __device__ inline void publish(Smem &L, int n)
 __device__ inline bool wait_pub(Smem &L, int s)
 {
     int spins = 0;
-    const int lim = (1 << 22) >> (wait_shift() > 22 ? 22 : wait_shift());
+    const int lim = L.pub_spins;
     while (__hip_atomic_load(&L.pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= s) {
         __builtin_amdgcn_s_sleep(1);
         if (++spins > lim) return false;
@@ -1037,7 +1044,16 @@ __global__ __launch_bounds__(kThreads) void bj_kernel(BjArgs A, int res)
     const int w = (int)(blockIdx.x >> 3);
     const int tid = threadIdx.x;
     const int P = A.nb / 2, G = P * A.Q;
-    if (tid == 0) { L.st_bad = 0; L.st_fail = 0; L.st_cnt = 0; L.pub = 0; }
+    if (tid == 0) {
+        L.st_bad = 0;
+        L.st_fail = 0;
+        L.st_cnt = 0;
+        L.pub = 0;
+        // The wait bounds, read once per launch (see g_wait_shift).
+        const int sh = wait_shift();
+        L.wait_ticks = kWaitTicks >> sh;
+        L.pub_spins = (1 << 22) >> (sh > 22 ? 22 : sh);
+    }
 
     // XCD check: every participant publishes its XCD id, one device-scope
     // barrier, then the same decision everywhere.
