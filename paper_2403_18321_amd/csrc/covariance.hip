@@ -500,11 +500,12 @@ __global__ __launch_bounds__(kThreads) void cov_partial_kernel(
 
 // The split products of one 32-pixel stage for a wave's S blocks, from the
 // hi / lo tiles in LDS (hi at hl, lo kHalf further; block e's operand rows at
-// offI[e], offJ[e]). The (k-step, block) items run in order, and the
-// operands of the next item are read while the products of this one run.
+// offI[e], offJ[e]); only the first ne slots hold blocks (the rest are
+// skipped). The (k-step, block) items run in order, and the operands of the
+// next item are read while the products of this one run.
 template <int MODE, int S>
 __device__ __forceinline__ void split_block_products(const __bf16 *hl, const int (&offI)[S], const int (&offJ)[S],
-                                                     f32x16 (&acc)[S])
+                                                     f32x16 (&acc)[S], int ne = S)
 {
     constexpr int kHalf = 256 * kBfPitch;
     constexpr int kItems = (KT / 16) * S;
@@ -519,10 +520,11 @@ __device__ __forceinline__ void split_block_products(const __bf16 *hl, const int
     operands(0, cur);
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-        if (it + 1 < kItems) operands(it + 1, nxt);
-        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
         const int e = it - (it / S) * S;
-        acc[e] = split_products<MODE>(cur[0], cur[1], cur[2], cur[3], acc[e]);
+        const int en = (it + 1) - ((it + 1) / S) * S;
+        if (it + 1 < kItems && en < ne) operands(it + 1, nxt);
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+        if (e < ne) acc[e] = split_products<MODE>(cur[0], cur[1], cur[2], cur[3], acc[e]);
         __builtin_amdgcn_sched_barrier(0);
         if (it + 1 < kItems) {
 #pragma unroll
@@ -716,6 +718,9 @@ __device__ __forceinline__ void cov_dma_body(
     // Operand offsets of this wave's blocks (slot e: id kDmaWaves e + wave; a
     // slot past the last block repeats block (0, 0) and is never stored).
     const int nbl = nb * (nb + 1) / 2;
+    // Slots that hold a block (a prefix: the ids grow with the slot); the
+    // products of the others are skipped.
+    const int nslots = nbl - wave <= 0 ? 0 : ((nbl - wave + kDmaWaves - 1) / kDmaWaves < S ? (nbl - wave + kDmaWaves - 1) / kDmaWaves : S);
     int offI[S], offJ[S];
 #pragma unroll
     for (int e = 0; e < S; ++e) {
@@ -781,27 +786,33 @@ __device__ __forceinline__ void cov_dma_body(
         if constexpr (MODE == MODE_F32) {
             // The operands of pixel pair kk + 1 are read while the products
             // of pair kk run, so that no product waits for its LDS reads.
-            float xa[S], xb[S];
+            // Slots past nslots hold no block and are skipped.
+            float xa[S] = {}, xb[S] = {};
 #pragma unroll
             for (int e = 0; e < S; ++e) {
-                xa[e] = load_elem(R + (lane >> 5) * pitch + offI[e]);
-                xb[e] = load_elem(R + (lane >> 5) * pitch + offJ[e]);
+                if (e < nslots) {
+                    xa[e] = load_elem(R + (lane >> 5) * pitch + offI[e]);
+                    xb[e] = load_elem(R + (lane >> 5) * pitch + offJ[e]);
+                }
             }
 #pragma unroll
             for (int kk = 0; kk < KT / 2; ++kk) {
-                float ya[S], yb[S];
+                float ya[S] = {}, yb[S] = {};
                 if (kk + 1 < KT / 2) {
                     const T *tr = R + (2 * kk + 2 + (lane >> 5)) * pitch;
 #pragma unroll
                     for (int e = 0; e < S; ++e) {
-                        ya[e] = load_elem(tr + offI[e]);
-                        yb[e] = load_elem(tr + offJ[e]);
+                        if (e < nslots) {
+                            ya[e] = load_elem(tr + offI[e]);
+                            yb[e] = load_elem(tr + offJ[e]);
+                        }
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
 #pragma unroll
                 for (int e = 0; e < S; ++e)
-                    acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[e] - shI[e], xb[e] - shJ[e], acc[e], 0, 0, 0);
+                    if (e < nslots)
+                        acc[e] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[e] - shI[e], xb[e] - shJ[e], acc[e], 0, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);
                 if (kk + 1 < KT / 2) {
 #pragma unroll
@@ -812,7 +823,7 @@ __device__ __forceinline__ void cov_dma_body(
                 }
             }
         } else {
-            split_block_products<MODE, S>(hl, offI, offJ, acc);
+            split_block_products<MODE, S>(hl, offI, offJ, acc, nslots);
         }
     };
 
@@ -1000,6 +1011,9 @@ __device__ __forceinline__ void cov_bsq_body(
         for (int r = 0; r < 16; ++r) acc2[e][r] = 0.f;
     }
     const int nbl = nb * (nb + 1) / 2;
+    // Slots that hold a block (a prefix: the ids grow with the slot).
+    const int nrem = nbl - idbase - wave;
+    const int nslots = nrem <= 0 ? 0 : ((nrem + kDmaWaves - 1) / kDmaWaves < S ? (nrem + kDmaWaves - 1) / kDmaWaves : S);
     int offI[S], offJ[S];
 #pragma unroll
     for (int e = 0; e < S; ++e) {
@@ -1062,7 +1076,7 @@ __device__ __forceinline__ void cov_bsq_body(
                 }
             }
         } else {
-            split_block_products<MODE, S>(hl, offI, offJ, acc);
+            split_block_products<MODE, S>(hl, offI, offJ, acc, nslots);
         }
         __syncthreads();
     };
@@ -1193,6 +1207,8 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
         for (int r = 0; r < 16; ++r) acc[e][r] = 0.f;
     }
     const int nbl = nb * (nb + 1) / 2;
+    // Slots that hold a block (a prefix: the ids grow with the slot).
+    const int nslots = nbl - wave <= 0 ? 0 : ((nbl - wave + kDmaWaves - 1) / kDmaWaves < S ? (nbl - wave + kDmaWaves - 1) / kDmaWaves : S);
     int offI[S], offJ[S];
 #pragma unroll
     for (int e = 0; e < S; ++e) {
@@ -1230,7 +1246,7 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
         }
     };
 
-    auto products = [&]() { split_block_products<MODE, S>(hl, offI, offJ, acc); };
+    auto products = [&]() { split_block_products<MODE, S>(hl, offI, offJ, acc, nslots); };
 
     // As in cov_partial_dma_kernel: wait for this stage's copies, barrier,
     // start the copies two stages ahead into the slot read last step,
