@@ -848,13 +848,19 @@ __device__ __forceinline__ void cov_dma_body(
         // One stage in ring slot `cur`; the copies for two stages ahead go
         // into `nxt` (the slot of the previous stage, which every wave has
         // finished reading once past the barrier).
+        // Each wave centres only its own rows, so once past the barrier the
+        // band sums and the products of a stage may come in either order:
+        // waves 4-7 multiply first, so that the two waves of a SIMD (w and
+        // w + 4) overlap one's centring with the other's products.
         T *const raw2 = DmaLds<T, MODE>::template ring<2>();
+        const bool prod_first = (wave & 4) != 0;
         auto step = [&](T *cur, T *nxt, int64_t st) {
             wait_one();
             lds_barrier();
             issue(nxt, st + 2);
+            if (prod_first && (!kSkip || nbl > wave)) products(cur, nullptr);
             centre(cur, nullptr);
-            if (!kSkip || nbl > wave) products(cur, nullptr);
+            if (!prod_first && (!kSkip || nbl > wave)) products(cur, nullptr);
             if ((st + 1) % kFlush == 0) {
 #pragma unroll
                 for (int e = 0; e < S; ++e) {
