@@ -64,6 +64,12 @@ __device__ __forceinline__ void project_stream_body(const T *__restrict__ Y, int
         vsh[sk][l] = (b < m && o < k) ? V[(int64_t)b * m + o] : 0.f;
     }
     __syncthreads();
+    // This lane's four band means (the 16-byte path reads bands 4 lane ..
+    // 4 lane + 3 of every row): held in registers, since reading them from
+    // LDS at a stride of four words would conflict on the banks.
+    f32x4 mu4;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) mu4[s] = mu[(4 * lane + s) & 255];
     const float *bcol = &vsh[s0][lane];
 
     const float *arow = &tile[(16 * gq + (lane & 15)) * pitch + 4 * s0 + (lane >> 4)];
@@ -78,7 +84,7 @@ __device__ __forceinline__ void project_stream_body(const T *__restrict__ Y, int
                 for (int i = 0; i < 8; ++i) {
                     f32x4 q;
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) q[s] = (b + s < m && pg + i < n) ? v.get(i, s) - mu[b + s] : 0.f;
+                    for (int s = 0; s < 4; ++s) q[s] = (b + s < m && pg + i < n) ? v.get(i, s) - mu4[s] : 0.f;
                     *reinterpret_cast<f32x4 *>(&tile[(8 * wave + i) * pitch + b]) = q;
                 }
             }
