@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kSetupThreads) void batch_setup_kernel(const pca_cu
         c.V = d.V;
         c.Q = d.Q;
         c.info = d.info;
-        c.cov = cov_plan_chunk(c.n, c.m, cov_chunk);
+        c.cov = batch_cov_plan(c.n, c.m, cov_chunk);
         const JacPlan jp = jac_plan(c.m, max_sweeps);
         char *a = area;
         c.partS = reinterpret_cast<float *>(a);

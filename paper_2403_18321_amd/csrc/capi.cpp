@@ -71,7 +71,7 @@ pca_status batch_plan(const pca_cube *cubes, int32_t n_cubes, int32_t max_sweeps
         if (c.k < 1 || c.k > c.n_bands || !c.mean || !c.eigvals || !c.V || !c.Q) return PCA_ERR_ARG;
         if (!aligned(c.mean, 4) || !aligned(c.eigvals, 4) || !aligned(c.V, 4) || !aligned(c.Q, 4)) return PCA_ERR_ARG;
         if (c.info && !aligned(c.info, 8)) return PCA_ERR_ARG;
-        const pca::CovPlan cp = pca::cov_plan_chunk(c.n_pixels, c.n_bands, chunk);
+        const pca::CovPlan cp = pca::batch_cov_plan(c.n_pixels, c.n_bands, chunk);
         const pca::JacPlan jp = pca::jac_plan(c.n_bands, max_sweeps);
         b += pca::batch_cube_bytes(cp, jp, c.n_bands);
         int64_t cnt[6];

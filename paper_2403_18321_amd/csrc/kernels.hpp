@@ -54,6 +54,18 @@ __host__ __device__ inline CovPlan cov_plan_chunk(int64_t n, int m, int64_t chun
     return p;
 }
 
+// The batched form's plan for one cube: at most two chunk groups in the
+// finalisation (a batch has work items enough without more, and each item
+// carries a fixed cost of table search and band means).
+constexpr int kBatchFinGroups = 2;
+__host__ __device__ inline CovPlan batch_cov_plan(int64_t n, int m, int64_t chunk)
+{
+    CovPlan p = cov_plan_chunk(n, m, chunk);
+    p.groups = (int)(p.nchunks < kBatchFinGroups ? p.nchunks : kBatchFinGroups);
+    p.bytes_part2 = ((size_t)p.groups * p.nblk * 1024 + 1 + 256) * sizeof(double);
+    return p;
+}
+
 // Pass 0: the shift row (written to srow, read by pass 1).
 hipError_t launch_cov_shift(const void *Y, int dt, int64_t n, int m, int64_t ld, const CovPlan &plan, float *srow,
                             hipStream_t st);
