@@ -537,12 +537,13 @@ __device__ __forceinline__ void split_block_products(const __bf16 *hl, const int
 //
 // The same chunk algorithm, organised for this case:
 //  * the raw pixel rows go from HBM straight into LDS through the load unit
-//    (global_load_lds_dwordx4: lane l's 16 bytes land at base + 16 l),
-//    kRing - 1 stages ahead of use, so no registers are tied up by loads in
-//    flight. The ring slots are three separate LDS arrays used in a fixed
-//    rotation, which lets the compiler see that reading one slot does not
-//    wait on the copies into the others; the copy waits (vmcnt) and the
-//    barriers are explicit;
+//    (global_load_lds_dwordx4: lane l's 16 bytes land at base + 16 l), two
+//    stages ahead of use, so no registers are tied up by loads in flight.
+//    The FP32 form rotates three ring slots (kRing); the split forms two
+//    slots plus two sets of hi / lo tiles. The slots are separate LDS arrays
+//    used in a fixed rotation, which lets the compiler see that reading one
+//    does not wait on the copies into the others; the copy waits (vmcnt) and
+//    the barriers are explicit;
 //  * 8 waves of modest register use, two per SIMD, so that one wave's
 //    centring and splitting overlaps another's matrix products;
 //  * rows past the chunk end, and lanes past the last band, copy the shift
@@ -716,7 +717,8 @@ __device__ __forceinline__ void cov_dma_body(
     }
 
     // Operand offsets of this wave's blocks (slot e: id kDmaWaves e + wave; a
-    // slot past the last block repeats block (0, 0) and is never stored).
+    // slot past the last block points at block (0, 0), is skipped by the
+    // products and is never stored).
     const int nbl = nb * (nb + 1) / 2;
     // Slots that hold a block (a prefix: the ids grow with the slot); the
     // products of the others are skipped.
@@ -1254,9 +1256,10 @@ __global__ __launch_bounds__(kDmaThreads) void cov_partial_bsq_dma_kernel(
 
     auto products = [&]() { split_block_products<MODE, S>(hl, offI, offJ, acc, nslots); };
 
-    // As in cov_partial_dma_kernel: wait for this stage's copies, barrier,
-    // start the copies two stages ahead into the slot read last step,
-    // centre and split, barrier, multiply.
+    // Wait for this stage's copies, barrier, start the copies two stages
+    // ahead into the slot read last step, centre and split, barrier,
+    // multiply (one tile set; cov_partial_dma_kernel's split forms keep two
+    // and need one barrier a stage).
     auto step = [&](T *cur, T *nxt, int64_t st) {
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(kBsqCopies));
         lds_barrier();
